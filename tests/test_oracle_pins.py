@@ -1,0 +1,402 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these checks retypes the oracle's formulas: kernel constants come from
+numerical quadrature of the normalisation requirement (the kernel integrates
+to one, Section "Smoothed Particle Hydrodynamics"), gradients and Laplacians
+from finite differences of those quadrature-normalised kernels, orders from
+numpy's lexsort, and boid / integration cases from hand arithmetic.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2311_15088_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _params(h=0.05, **kw):
+    p = scenes.default_params(h, 5e-4, (0, 0, 0), (1, 1, 1))
+    p.update(kw)
+    return p
+
+
+def _ball_norm(shape, h, n=40):
+    """1 / (4 pi int_0^h r^2 shape(r) dr) by Gauss-Legendre quadrature."""
+    t, w = np.polynomial.legendre.leggauss(n)
+    r = 0.5 * h * (t + 1.0)
+    return 1.0 / (4.0 * math.pi * np.sum(0.5 * h * w * r * r * shape(r)))
+
+
+def _poly6_c(h):
+    return _ball_norm(lambda r: (h * h - r * r) ** 3, h)
+
+
+def _spiky(h):
+    c = _ball_norm(lambda r: (h - r) ** 3, h)
+    return lambda r: c * (h - r) ** 3
+
+
+def _visc(h):
+    shape = lambda r: -r ** 3 / (2 * h ** 3) + r ** 2 / h ** 2 + h / (2 * r) - 1.0  # noqa: E731
+    c = _ball_norm(shape, h)
+    return lambda r: c * shape(r)
+
+
+def _d1(f, r, e):
+    return (f(r + e) - f(r - e)) / (2 * e)
+
+
+def _laplacian_radial(f, r, e):
+    d2 = (f(r + e) - 2 * f(r) + f(r - e)) / (e * e)
+    return d2 + 2.0 * _d1(f, r, e) / r
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+def _one(p, x, v, y=None, u=None, **kw):
+    y = np.zeros((0, 3), np.float32) if y is None else _f32(y)
+    u = np.zeros((0, 3), np.float32) if u is None else _f32(u)
+    return oracle.step(p, _f32(x), _f32(v), y, u, **kw)
+
+
+# ---------------------------------------------------------------- kernels ---
+
+def test_poly6_normalisation_by_quadrature():
+    """An isolated particle's density is m W(0); W must integrate to one over the ball."""
+    h = 0.05
+    p = _params(h)
+    r = _one(p, [[0.5, 0.5, 0.5]], [[0, 0, 0]])
+    c6_oracle = r["rho"][0] / (p["mass"] * np.float64(np.float32(h)) ** 6)
+    hh = float(np.float32(h))
+    assert c6_oracle == pytest.approx(_poly6_c(hh), rel=1e-12)
+
+
+def test_lattice_density_golden_and_self_term():
+    """Unjittered s = h/2 lattice interior density (golden value, self included)."""
+    vals = dict(line.split() for line in open(os.path.join(GOLDEN, "lattice_density.txt"))
+                if line.strip() and not line.startswith("#"))
+    h = 0.0625  # a power of two: every lattice site is exact in float32
+    p = _params(h)
+    pts = scenes.lattice(9, 9, 9, 0.5 * h, (0.25, 0.25, 0.25))
+    centre = 4 + 9 * (4 + 9 * 4)
+    r = _one(p, pts, np.zeros_like(pts), fsample=np.array([centre]))
+    assert r["rho"][centre] == pytest.approx(float(vals["rho_interior"]), rel=1e-13)
+    assert r["nbr"][centre] == 26
+    # independent route: enumerate lattice offsets, quadrature-normalised poly6
+    hh = float(np.float32(h))
+    off = np.array([(a, b, c) for a in range(-2, 3) for b in range(-2, 3) for c in range(-2, 3)], float) * 0.5
+    q2 = (off ** 2).sum(1)
+    ksum = np.sum(np.where(q2 < 1.0, (1.0 - q2) ** 3, 0.0))
+    assert ksum == pytest.approx(float(vals["kernel_sum"]), rel=1e-15)
+    expect = p["mass"] * _poly6_c(hh) * hh ** 6 * ksum
+    assert r["rho"][centre] == pytest.approx(expect, rel=1e-12)
+
+
+def test_density_tends_to_continuum_on_fine_lattice():
+    """With spacing h/6 and m = rho0 s^3 the kernel sum recovers rho0 (int W = 1)."""
+    h = 0.06
+    s = h / 6.0
+    p = _params(h, mass=float(np.float32(1000.0 * s ** 3)))
+    n = 25
+    pts = scenes.lattice(n, n, n, s, (0.3, 0.3, 0.3))
+    c = n // 2
+    centre = c + n * (c + n * c)
+    r = _one(p, pts, np.zeros_like(pts), fsample=np.array([centre]), nbr_mode=1)
+    assert r["rho"][centre] == pytest.approx(1000.0 * p["mass"] / float(np.float32(1000.0 * s ** 3)), rel=2e-3)
+
+
+def _two(h, r, rho0, k, mu, v1=(0, 0, 0), v2=(0, 0, 0), norm=0):
+    p = _params(h, rest_density=rho0, gas_k=k, viscosity=mu, kernel_norm=norm, gravity=[0, 0, 0])
+    x = np.array([[0.5, 0.5, 0.5], [0.5 + r, 0.5, 0.5]], np.float32)
+    v = np.array([v1, v2], np.float32)
+    out = _one(p, x, v)
+    return p, x.astype(np.float64), v.astype(np.float64), out
+
+
+def test_pressure_force_matches_spiky_gradient():
+    """Two particles: a_1 = -(m/rho_1) (p_1 + p_2)/(2 rho_2) grad W_spiky(x_1 - x_2)."""
+    h = 0.05
+    p, x, v, out = _two(h, 0.02, rho0=100.0, k=3.0, mu=0.0)
+    hh, m = float(np.float32(h)), p["mass"]
+    rvec = x[0] - x[1]
+    r = np.linalg.norm(rvec)
+    rho = m * _poly6_c(hh) * (hh ** 6 + (hh * hh - r * r) ** 3)
+    assert out["rho"][0] == pytest.approx(rho, rel=1e-9)
+    pr = 3.0 * (rho - 100.0)
+    grad = _d1(_spiky(hh), r, 1e-7) * rvec / r
+    expect = -m * (pr + pr) / (2 * rho) * grad / rho
+    np.testing.assert_allclose(out["a_int"][0], expect, rtol=1e-6, atol=1e-9 * np.abs(expect).max())
+    # compressed pair repels: particle 0 (at lower x) is pushed towards -x
+    assert out["a_int"][0, 0] < 0 < out["a_int"][1, 0]
+
+
+def test_viscosity_matches_laplacian_and_damps():
+    """Two particles, no pressure: a_1 = (mu/rho_1) m (v_2 - v_1)/rho_2 lap W_visc(r)."""
+    h = 0.05
+    p, x, v, out = _two(h, 0.03, rho0=1000.0, k=0.0, mu=0.1, v1=(0.2, -0.1, 0.05), v2=(-0.1, 0.0, 0.3))
+    hh, m = float(np.float32(h)), p["mass"]
+    r = np.linalg.norm(x[0] - x[1])
+    rho = m * _poly6_c(hh) * (hh ** 6 + (hh * hh - r * r) ** 3)
+    lap = _laplacian_radial(_visc(hh), r, 1e-5)
+    expect = 0.1 * m * (v[1] - v[0]) / rho * lap / rho
+    np.testing.assert_allclose(out["a_int"][0], expect, rtol=1e-5)
+    # damping: acceleration opposes the relative velocity
+    assert np.dot(out["a_int"][0], v[0] - v[1]) < 0
+
+
+def test_paper_literal_kernel_constants():
+    """kernel_norm 1 reproduces the printed combined pressure + viscosity expression
+    (Section "Pressure and Viscosity"); those constants normalise in 2-D, not 3-D."""
+    h = 0.05
+    p, x, v, out = _two(h, 0.02, rho0=100.0, k=3.0, mu=0.1, v1=(0.1, 0, 0), v2=(0, 0.2, 0), norm=1)
+    hh, m = float(np.float32(h)), p["mass"]
+    rij = x[0] - x[1]
+    q = np.linalg.norm(rij) / hh
+    rho = out["rho"]
+    printed = m * (1 - q) / (math.pi * hh ** 4 * rho[1]) * (
+        15 * 3.0 * (rho[0] + rho[1] - 200.0) * (1 - q) * rij / q - 40 * float(np.float32(0.1)) * (v[0] - v[1]))
+    np.testing.assert_allclose(out["a_int"][0] * rho[0], printed, rtol=1e-9)
+    # 30/(pi h^4) (1-q)^2 / q * r is grad of 10/(pi h^5)(h-r)^3 -- a 2-D normalised kernel
+    t, w = np.polynomial.legendre.leggauss(20)
+    rr = 0.5 * hh * (t + 1)
+    assert np.sum(0.5 * hh * w * 2 * math.pi * rr * 10 / (math.pi * hh ** 5) * (hh - rr) ** 3) == pytest.approx(1.0)
+
+
+# -------------------------------------------------------------- invariants ---
+
+def test_momentum_conservation_internal_force():
+    sc = scenes.small_dam(agents="inside")
+    rng = np.random.default_rng(1)
+    v = (0.3 * rng.standard_normal(sc.x.shape)).astype(np.float32)
+    r = oracle.step(sc.params, sc.x, v, sc.y[:0], sc.u[:0])
+    m = sc.params["mass"]
+    tot = (m * r["a_int"]).sum(0)
+    scale = np.abs(m * r["a_int"]).sum()
+    assert np.all(np.abs(tot) < 1e-12 * scale)
+
+
+def test_rest_lattice_interior_has_no_internal_force():
+    h = 0.0625
+    p = _params(h)
+    pts = scenes.lattice(9, 9, 9, 0.5 * h, (0.25, 0.25, 0.25))
+    centre = 4 + 9 * (4 + 9 * 4)
+    r = _one(p, pts, np.zeros_like(pts), fsample=np.array([centre]))
+    # one pair term is O(k (rho - rho0) / (rho h)) ~ 1; symmetry cancels it
+    assert np.abs(r["a_int"][centre]).max() < 1e-9
+
+
+def test_coupling_action_reaction():
+    sc = scenes.config0c()
+    r = oracle.step(sc.params, sc.x, sc.v + 0.1, sc.y, sc.u)
+    tot = r["force"].sum(0) + sc.params["mass"] * r["a_coup"].sum(0)
+    assert np.all(np.abs(tot) < 1e-12 * np.abs(r["force"]).sum())
+    assert r["touched"].sum() == r["n_cpl"].sum()
+
+
+def test_agents_do_not_change_fluid_density():
+    sc = scenes.config0c()
+    a = oracle.step(sc.params, sc.x, sc.v, sc.y, sc.u)
+    b = oracle.step(sc.params, sc.x, sc.v, sc.y[:0], sc.u[:0])
+    np.testing.assert_array_equal(a["rho"], b["rho"])
+
+
+def test_single_agent_single_particle_coupling():
+    """Agent = particle of mass m at rest density (p_a = 0) interacting through the
+    quadrature-normalised spiky and viscosity kernels at the coupling radius."""
+    h = 0.05
+    p = _params(h, gravity=[0, 0, 0], rest_density=100.0)
+    rc = float(np.float32(p["r_couple"]))
+    x = np.array([[0.5, 0.5, 0.5]], np.float32)
+    v = np.array([[0.0, 0.1, 0.0]], np.float32)
+    y = np.array([[0.5 + 0.06, 0.5 + 0.01, 0.5]], np.float32)
+    u = np.array([[0.3, -0.2, 0.1]], np.float32)
+    r = _one(p, x, v, y, u)
+    m = p["mass"]
+    hh = float(np.float32(h))
+    rho_j = m * _poly6_c(hh) * hh ** 6  # isolated particle (agents add no density)
+    assert r["rho"][0] == pytest.approx(rho_j, rel=1e-9)
+    d = y[0].astype(float) - x[0].astype(float)
+    dist = np.linalg.norm(d)
+    pj = 3.0 * (rho_j - 100.0)
+    f_p = -m * (0.0 + pj) / (2 * rho_j) * _d1(_spiky(rc), dist, 1e-7) * d / dist
+    f_v = float(np.float32(0.1)) * m * (v[0] - u[0]).astype(float) / rho_j * _laplacian_radial(_visc(rc), dist, 1e-5)
+    F = (m / 100.0) * (f_p + f_v)  # force = (m_a / rho_a) x force density
+    np.testing.assert_allclose(r["force"][0], F, rtol=1e-5)
+    np.testing.assert_allclose(r["a_coup"][0], -F / m, rtol=1e-5)
+    assert r["n_cpl"][0] == 1 and r["touched"][0] == 1
+
+
+# ------------------------------------------------------- keys, order, sets ---
+
+def test_keys_and_order_match_lexsort():
+    sc = scenes.small_dam()
+    p = sc.params
+    r = oracle.step(p, sc.x, sc.v, sc.y, sc.u)
+    dims, cell, inv, nc = oracle.grid(p)
+    t = (sc.x - np.asarray(p["box_min"], np.float32)).astype(np.float32) * np.float32(inv)
+    c = np.clip(np.floor(t).astype(np.int64), 0, np.asarray(dims) - 1)
+    key = c[:, 0] + dims[0] * (c[:, 1] + dims[1] * c[:, 2])
+    np.testing.assert_array_equal(r["key"], key)
+    ids = np.arange(sc.n)
+    np.testing.assert_array_equal(r["sorted"], np.lexsort((ids, key)))
+    np.testing.assert_array_equal(r["cnt"], np.bincount(key, minlength=nc))
+    assert r["off"][0] == 0 and r["off"][-1] == sc.n and np.all(np.diff(r["off"].astype(np.int64)) >= 0)
+    assert dims == (20, 16, 20)
+    assert cell == np.float32(0.05 * (1 + 2 ** -10))
+
+
+def test_brute_force_and_cell_list_agree_with_adversarial_pairs():
+    """Cell-list neighbour sets equal the brute-force definition, including pairs
+    placed one float32 ulp either side of the cut-off and on cell faces."""
+    sc = scenes.small_dam(agents="inside")
+    p = sc.params
+    h2 = np.float32(np.float64(np.float32(p["h"])) ** 2)
+    rng = np.random.default_rng(7)
+    extra = []
+    for _ in range(60):
+        a = rng.uniform(0.1, 0.6, 3).astype(np.float32)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        for scale in (1.0 - 2e-7, 1.0, 1.0 + 2e-7):
+            b = (a + d * np.sqrt(float(h2)) * scale).astype(np.float32)
+            extra += [a, b]
+    x = np.concatenate([sc.x, np.array(extra, np.float32)])
+    v = np.zeros_like(x)
+    a = oracle.step(p, x, v, sc.y, sc.u, nbr_mode=0)
+    b = oracle.step(p, x, v, sc.y, sc.u, nbr_mode=1)
+    for k in ("nbr", "rho", "a_int", "a_coup", "force", "n_cpl", "touched"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_cutoff_is_strict_in_float32():
+    h = 0.05
+    p = _params(h)
+    h2 = np.float32(np.float64(np.float32(h)) ** 2)
+    # find d with fl32(d*d) == h2 exactly, and its predecessor
+    d = np.float32(np.sqrt(np.float64(h2)))
+    while np.float32(d * d) > h2:
+        d = np.nextafter(d, np.float32(0))
+    while np.float32(d * d) < h2:
+        d = np.nextafter(d, np.float32(1))
+    if np.float32(d * d) == h2:
+        x0 = np.float32(0.25)
+        for dd, expect in ((d, 0), (np.nextafter(d, np.float32(0)), 1)):
+            x1 = np.float32(x0 + dd)
+            dx = np.float32(x1 - x0)
+            r = _one(p, [[x0, 0.5, 0.5], [x1, 0.5, 0.5]], np.zeros((2, 3)))
+            assert r["nbr"][0] == (1 if np.float32(dx * dx) < h2 else 0)
+    else:  # no exact square: still strictly below
+        pytest.skip("no float32 with an exact square equal to h^2")
+
+
+# ------------------------------------------------------------ integration ---
+
+def test_free_fall_is_symplectic_euler():
+    p = _params(0.05)
+    dt = float(np.float32(p["dt"]))
+    g = float(np.float32(-9.81))
+    x0 = np.array([[0.5, 0.5, 0.9]], np.float32)
+    v0 = np.array([[0.1, 0.0, 0.2]], np.float32)
+    r = _one(p, x0, v0)
+    v1 = v0[0].astype(float) + np.array([0, 0, g]) * dt
+    x1 = x0[0].astype(float) + dt * v1  # position uses the new velocity
+    np.testing.assert_allclose(r["v1"][0], v1, rtol=1e-15, atol=1e-17)
+    np.testing.assert_allclose(r["x1"][0], x1, rtol=1e-15)
+    # 40 steps through float32 states vs x_n = x0 + n v0 dt + g dt^2 n (n + 1) / 2
+    x, v = x0, v0
+    for _ in range(40):
+        r = _one(p, x, v)
+        x, v = r["x1"].astype(np.float32), r["v1"].astype(np.float32)
+    n = 40
+    xz = 0.9 + n * 0.2 * dt + g * dt * dt * n * (n + 1) / 2
+    assert x[0, 2] == pytest.approx(xz, rel=1e-6)
+    assert v[0, 2] == pytest.approx(0.2 + n * g * dt, rel=1e-5)
+
+
+def test_wall_reflection_hand_cases():
+    p = _params(0.05, gravity=[0, 0, 0], dt=0.01, wall_restitution=0.5)
+    x = np.array([[0.001, 0.5, 0.5], [0.5, 0.998, 0.5]], np.float32)
+    v = np.array([[-0.3, 0.0, 0.0], [0.0, 0.5, 0.0]], np.float32)
+    r = _one(p, x, v)
+    dt = float(np.float32(0.01))
+    # x' = 0.001 - 0.003 = -0.002 -> reflected to +0.002, v -> +0.15
+    assert r["x1"][0, 0] == pytest.approx(-(float(x[0, 0]) - 0.3 * dt), rel=1e-6)
+    assert r["v1"][0, 0] == pytest.approx(0.15, rel=1e-6)
+    # y' = 0.998 + 0.005 = 1.003 -> 2 - 1.003 = 0.997, v -> -0.25
+    assert r["x1"][1, 1] == pytest.approx(2.0 - (float(x[1, 1]) + float(np.float32(0.5)) * dt), rel=1e-6)
+    assert r["v1"][1, 1] == pytest.approx(-0.25, rel=1e-6)
+
+
+# -------------------------------------------------------------- boid rules ---
+
+def _agents(p, y, u):
+    x = np.array([[0.9, 0.9, 0.9]], np.float32)  # one far-away fluid particle
+    return _one(p, x, np.zeros((1, 3)), y, u)
+
+
+def test_boids_collinear_case():
+    """Agents at x = 0.30, 0.35, 0.45 (h = 0.05: r_sep 0.1, visual range 0.2)."""
+    p = _params(0.05, gravity=[0, 0, 0])
+    y = np.array([[0.30, 0.5, 0.5], [0.35, 0.5, 0.5], [0.45, 0.5, 0.5]], np.float32)
+    u = np.array([[0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5]], np.float32)
+    r = _agents(p, y, u)
+    Y = y.astype(float)
+    U = u.astype(float)
+    # agent 0: separation from agent 1 only (0.05 < 0.1), weight 1 - 0.05/0.1 = 0.5
+    sep0 = (1 - (Y[1, 0] - Y[0, 0]) / float(np.float32(0.1))) * (Y[0] - Y[1])
+    ali0 = 0.5 * (U[1] + U[2]) - U[0]
+    coh0 = 0.5 * (Y[1] + Y[2]) - Y[0]
+    np.testing.assert_allclose(r["steer"][0], 1.5 * sep0 + ali0 + coh0, rtol=1e-9, atol=1e-12)
+    # agent 2: nothing within 0.1 (0.10 apart from agent 1 is not < 0.1 after rounding? check both ways)
+    d21 = np.float32(y[1, 0] - y[2, 0])
+    in_sep = np.float32(d21 * d21) < np.float32(float(np.float32(0.1)) ** 2)
+    assert r["n_sep"][2] == int(in_sep)
+    assert list(r["n_ali"]) == [2, 2, 2] and list(r["n_coh"]) == [2, 2, 2]
+    assert r["n_sep"][0] == 1 and r["n_sep"][1] == 1 + int(in_sep)
+
+
+def test_boids_equilateral_case_and_isolated_agent():
+    p = _params(0.05, gravity=[0, 0, 0])
+    s = 0.08
+    c = np.array([0.5, 0.5, 0.5])
+    y = np.array([c + [0, 0, 0], c + [s, 0, 0], c + [s / 2, s * math.sqrt(3) / 2, 0], [0.1, 0.1, 0.1]],
+                 np.float32)
+    u = np.array([[0.3, 0.4, 0.0]] * 3 + [[0.0, 0.0, 0.5]], np.float32)
+    r = _agents(p, y, u)
+    Y = y.astype(float)
+    for a in range(3):
+        others = [b for b in range(3) if b != a]
+        sep = sum((1 - np.linalg.norm(Y[a] - Y[b]) / float(np.float32(0.1))) * (Y[a] - Y[b]) for b in others)
+        coh = Y[others].mean(0) - Y[a]
+        np.testing.assert_allclose(r["steer"][a], 1.5 * sep + coh, rtol=1e-9, atol=1e-12)
+        # separation points away from the centroid, alignment is zero
+        cen = Y[:3].mean(0)
+        assert np.dot(sep, Y[a] - cen) > 0
+    np.testing.assert_array_equal(r["steer"][3], 0.0)
+    assert r["n_ali"][3] == 0 and r["n_sep"][3] == 0
+    # isolated agent keeps its speed 0.5 (inside [0.25, 1]) and moves by dt u
+    dt = float(np.float32(p["dt"]))
+    np.testing.assert_allclose(r["u1"][3], u[3].astype(float), rtol=1e-12)
+    np.testing.assert_allclose(r["y1"][3], Y[3] + dt * u[3].astype(float), rtol=1e-12)
+
+
+def test_agent_speed_limits():
+    p = _params(0.05, gravity=[0, 0, 0], dt=0.5, w_sep=0.0, w_coh=0.0, w_ali=1.0)
+    # two agents 0.05 apart with opposite velocities: alignment drives each towards the mean (0)
+    y = np.array([[0.5, 0.5, 0.5], [0.55, 0.5, 0.5], [0.1, 0.1, 0.1]], np.float32)
+    u = np.array([[0.4, 0, 0], [-0.4, 0, 0], [0, 3.0, 0]], np.float32)
+    r = _agents(p, y, u)
+    # agent 0: u' = 0.4 + 0.5 * (-0.4 - 0.4) = 0.0 exactly -> zero stays zero
+    # agent 2 (isolated) keeps 3.0 then is clamped to v_max = 1
+    np.testing.assert_allclose(r["u1"][2], [0, 1.0, 0], rtol=1e-12)
+    p2 = _params(0.05, gravity=[0, 0, 0], dt=0.25, w_sep=0.0, w_coh=0.0, w_ali=1.0)
+    r2 = _agents(p2, y, u)
+    # u' = 0.4 + 0.25 * (-0.8) = 0.2 < v_min -> rescaled to 0.25
+    np.testing.assert_allclose(r2["u1"][0], [0.25, 0, 0], rtol=1e-6)
+    assert np.all(np.isfinite(r["u1"][:2]))
