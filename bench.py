@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark: SPH + boid time steps on one MI355X.
+
+Workload: the 1,048,576-particle dam break (128 x 64 x 128 lattice, s = 0.01,
+h = 0.02, box [0,3] x [0,1] x [0,3]) with 1,024 boid agents above the fluid,
+dt = 2e-4 -- seeded synthetic inputs, already resident in HBM when timing
+starts.  A step is one pass of the whole path: cell keys + counting sort,
+density, boid steering + coupling, forces + integration.
+
+Two regions run the same K steps from the same initial state:
+  * timed region: K steps with a HIP event recorded on the library's stream
+    after every kernel (per-kernel durations, the whole-step time);
+  * graph region: K steps replayed from captured HIP graphs (reported beside).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+# Algorithmic bytes per element and launch for each kernel of a step (the
+# arrays each kernel must read and write once, in the layout it uses).
+#   key_count      reads x,y,z (12), writes key, rank (8)             per particle
+#   scan_reduce    reads cnt (4)                                       per cell
+#   scan_sets      reads / writes chunk sums (8)                       per 4,096 cells
+#   scan_apply     reads cnt (4), writes off (4), clears cnt (4)       per cell
+#   scatter        reads key, rank, id (12), writes src, id (8)        per particle
+#   fixup_gather   reads src, id, key (12), x, v (24), writes x, v, id (28) per particle
+#   density        reads x (12), writes rho, n (8)                     per particle
+#   force_integrate reads x, v, rho (28), writes x', v' (24)           per particle
+#   agents         reads y, u (24), writes y', u' (24)                 per agent
+B_PER_PARTICLE = {"key_count": 20, "scatter": 20, "fixup_gather": 64, "density": 20, "force_integrate": 52}
+B_PER_CELL = {"scan_reduce": 4, "scan_apply": 12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, n, cells, agents):
+    if name in B_PER_PARTICLE:
+        return B_PER_PARTICLE[name] * n
+    if name in B_PER_CELL:
+        return B_PER_CELL[name] * cells
+    if name == "scan_sets":
+        return 8 * math.ceil(cells / 4096)
+    if name == "agents":
+        return 48 * agents
+    return 0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(sc, budget_s: float):
+    """The CPU oracle timed on the host cores on whole steps of the same workload."""
+    import oracle  # test infrastructure: only this leg of the bench uses it
+
+    x, v, y, u = sc.x, sc.v, sc.y, sc.u
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.step(sc.params, x, v, y, u, nbr_mode=1)
+        x, v = r["x1"].astype(np.float32), r["v1"].astype(np.float32)
+        y, u = r["y1"].astype(np.float32), r["u1"].astype(np.float32)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 20:
+            break
+    return {
+        "value": steps * sc.n / el, "unit": "particle-steps/s", "cores": oracle.threads(), "kind": "oracle",
+        "sample": f"{steps} whole step(s) of the same {sc.n}-particle workload from its initial state, FP64 "
+                  f"oracle with its cell-list neighbour finder (sets identical to brute force), "
+                  f"{oracle.threads()} OpenMP threads on '{cpu_model()}', {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=50, help="steps per captured graph in the graph region")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the step is single-device).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2311_15088_amd as sph
+    from paper_2311_15088_amd import scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sc = scenes.config1()
+    K, W = args.steps, args.warmup
+    log(f"[bench] workload c1: n={sc.n} agents={sc.n_agents} steps={K} warmup={W}")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    inputs = [torch.from_numpy(a).to(dev) for a in (sc.x, sc.v, sc.y, sc.u)]
+    torch.cuda.synchronize()
+
+    def make():
+        return sph.Simulation(sc.params, *inputs, stream=stream)
+
+    # ---- timed region: K steps, HIP events after every kernel ----
+    sim = make()
+    info = sim.info()
+    sim.step(W)
+    torch.cuda.synchronize()
+    pairs0 = int(sim.read(sph.PAIR_COUNT)[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phase_ms = sim.step_profiled(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = int(sim.read(sph.PAIR_COUNT)[0]) - pairs0
+    sim.close()
+    gpu_ms = sum(phase_ms.values())
+    ms_per_step = 1e3 * wall / K
+    log(f"[bench] timed region: {ms_per_step:.4f} ms/step wall, {gpu_ms / K:.4f} ms/step in kernels")
+    for k, vms in phase_ms.items():
+        log(f"[bench]   {k:16s} {1e3 * vms / K:9.2f} us/step")
+
+    # ---- graph region: same K steps replayed from captured graphs ----
+    graph_ms = None
+    if not args.no_graph:
+        sim = make()
+        sim.step(W)
+        c = max(1, min(args.chunk, K))
+        sim.capture(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done + c <= K:
+            sim.step(c)
+            done += c
+        if done < K:
+            sim.capture(0)
+            sim.step(K - done)
+        torch.cuda.synchronize()
+        graph_ms = 1e3 * (time.perf_counter() - t0) / K
+        sim.close()
+        log(f"[bench] graph region: {graph_ms:.4f} ms/step")
+
+    n, cells, agents = sc.n, info["cells"], sc.n_agents
+    value = K * n / wall
+    # whole-step HBM fraction with B_alg = 154 + 24 C/N bytes per particle-step
+    b_alg = 154.0 + 24.0 * cells / n
+    hbm_frac_step = b_alg * n / (ms_per_step * 1e-3) / (PEAK_HBM_GBS * 1e9)
+    dom = max(phase_ms, key=phase_ms.get)
+    t_dom = phase_ms[dom] / K * 1e-3
+    ach = kernel_bytes(dom, n, cells, agents) / t_dom / 1e9
+    result = {
+        "metric": "particle-steps/s & %HBM roofline @1M SPH+boid; batched & surrogate vs plain",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dam break 128x64x128 = 1,048,576 particles + 1,024 boids, h=0.02, dt=2e-4",
+                   "n": n, "agents": agents, "cells": cells},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM_GBS, "traffic": None},
+        "step_hbm_frac": hbm_frac_step,
+        "b_alg_bytes_per_particle_step": b_alg,
+        "pair_interactions_per_s": pairs / wall,
+        "mean_neighbours": pairs / (K * n),
+        "kernel_us_per_step": {k: 1e3 * vms / K for k, vms in phase_ms.items()},
+        "graph_ms_per_step": graph_ms,
+    }
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

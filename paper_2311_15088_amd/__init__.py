@@ -1,0 +1,254 @@
+"""MI355X-native SPH + boid time step -- Python binding of ``libsph.so``.
+
+This module only marshals arguments for the C ABI declared in
+``include/sph.h``; every step of the method runs in the library's HIP kernels.
+Importing it does not need a GPU; creating a simulation does, and fails loudly
+when ``libsph.so`` has not been built (``python -m paper_2311_15088_amd.build``).
+
+Inputs may be numpy arrays (host) or torch tensors (host or device); torch is
+used only for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsph.so")
+
+# status codes
+OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENONFINITE, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
+FLAG_DIAGNOSTICS, FLAG_CHECK_FINITE = 1, 2
+
+# fields (sph_field)
+POS, VEL, AGENT_POS, AGENT_VEL, DENSITY, NBR_COUNT, CELL_KEY, ACC_INT, ACC_COUPLE, TOUCHED, \
+    AGENT_FORCE, AGENT_STEER, AGENT_COUNTS, SORTED_IDS, CELL_OFFSETS, AGENT_KEY, AGENT_SORTED_IDS, \
+    AGENT_CELL_OFFSETS, PAIR_COUNT = range(19)
+
+_FIELD_DTYPE = {
+    POS: (np.float32, 3), VEL: (np.float32, 3), AGENT_POS: (np.float32, 3), AGENT_VEL: (np.float32, 3),
+    DENSITY: (np.float32, 1), NBR_COUNT: (np.uint32, 1), CELL_KEY: (np.uint32, 1), ACC_INT: (np.float32, 3),
+    ACC_COUPLE: (np.float32, 3), TOUCHED: (np.uint32, 1), AGENT_FORCE: (np.float32, 3),
+    AGENT_STEER: (np.float32, 3), AGENT_COUNTS: (np.uint32, 4), SORTED_IDS: (np.uint32, 1),
+    CELL_OFFSETS: (np.uint32, 1), AGENT_KEY: (np.uint32, 1), AGENT_SORTED_IDS: (np.uint32, 1),
+    AGENT_CELL_OFFSETS: (np.uint32, 1), PAIR_COUNT: (np.uint64, 1),
+}
+
+
+class SphError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"sph status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``sph_params``."""
+
+    _fields_ = [
+        ("h", ctypes.c_float), ("rest_density", ctypes.c_float), ("gas_k", ctypes.c_float),
+        ("viscosity", ctypes.c_float), ("mass", ctypes.c_float), ("dt", ctypes.c_float),
+        ("gravity", ctypes.c_float * 3), ("box_min", ctypes.c_float * 3), ("box_max", ctypes.c_float * 3),
+        ("wall_restitution", ctypes.c_float),
+        ("r_sep", ctypes.c_float), ("r_ali", ctypes.c_float), ("r_coh", ctypes.c_float),
+        ("w_sep", ctypes.c_float), ("w_ali", ctypes.c_float), ("w_coh", ctypes.c_float),
+        ("r_couple", ctypes.c_float), ("couple_factor", ctypes.c_float), ("v_min", ctypes.c_float),
+        ("v_max", ctypes.c_float), ("n_buckets", ctypes.c_uint32), ("kernel_norm", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("n_agents", ctypes.c_int64), ("dims", ctypes.c_int32 * 3),
+        ("agent_dims", ctypes.c_int32 * 3), ("cells", ctypes.c_int64), ("agent_cells", ctypes.c_int64),
+        ("cell", ctypes.c_float), ("agent_cell", ctypes.c_float), ("steps", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_bytes", "sph_info_get",
+           "sph_capture", "sph_step_profiled", "sph_phase_name", "sph_destroy", "sph_last_error")
+STEP_PHASES = 9
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsph.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_15088_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.sph_create.restype = ctypes.c_int
+        L.sph_create.argtypes = [ctypes.POINTER(Params), i64, vp, vp, i64, vp, vp, vp, ctypes.POINTER(vp)]
+        L.sph_create_batch.restype = ctypes.c_int
+        L.sph_create_batch.argtypes = [ctypes.POINTER(Params), i32, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.sph_step.restype = ctypes.c_int
+        L.sph_step.argtypes = [vp, i32]
+        L.sph_read.restype = ctypes.c_int
+        L.sph_read.argtypes = [vp, i32, vp, i64]
+        L.sph_field_bytes.restype = i64
+        L.sph_field_bytes.argtypes = [vp, i32]
+        L.sph_info_get.restype = ctypes.c_int
+        L.sph_info_get.argtypes = [vp, ctypes.POINTER(Info)]
+        L.sph_capture.restype = ctypes.c_int
+        L.sph_capture.argtypes = [vp, i32]
+        L.sph_step_profiled.restype = ctypes.c_int
+        L.sph_step_profiled.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i32]
+        L.sph_phase_name.restype = ctypes.c_char_p
+        L.sph_phase_name.argtypes = [i32]
+        L.sph_destroy.restype = None
+        L.sph_destroy.argtypes = [vp]
+        L.sph_last_error.restype = ctypes.c_char_p
+        L.sph_last_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def params(d: Dict, flags: int = 0) -> Params:
+    """Build an ``sph_params`` from a dict with the same field names."""
+    p = Params()
+    for name, _ in Params._fields_:
+        if name == "flags":
+            continue
+        val = d[name]
+        if isinstance(val, (list, tuple, np.ndarray)):
+            arr = getattr(p, name)
+            for k in range(3):
+                arr[k] = float(val[k])
+        elif name in ("n_buckets", "kernel_norm"):
+            setattr(p, name, int(val))
+        else:
+            setattr(p, name, float(val))
+    p.flags = int(flags) | int(d.get("flags", 0))
+    return p
+
+
+def _ptr(a):
+    """(pointer, keepalive) for a numpy array or torch tensor of float32 [n][3]."""
+    if a is None:
+        return None, None
+    if hasattr(a, "data_ptr"):  # torch tensor (host or device)
+        t = a.contiguous()
+        return (t.data_ptr() if t.numel() else None), t
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return (arr.ctypes.data if arr.size else None), arr
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = lib().sph_last_error(ctx).decode(errors="replace")
+        raise SphError(status, msg)
+
+
+class Simulation:
+    """One context: a single scene (``Simulation(...)``) or many (``Simulation.batch(...)``)."""
+
+    def __init__(self, p: Dict, x, v, y, u, stream: int = 0, flags: int = 0, _ctx=None):
+        self._ctx = _ctx
+        if _ctx is not None:
+            return
+        L = lib()
+        n = int(x.shape[0])
+        na = int(y.shape[0])
+        px, kx = _ptr(x)
+        pv, kv = _ptr(v)
+        py, ky = _ptr(y)
+        pu, ku = _ptr(u)
+        out = ctypes.c_void_p()
+        prm = params(p, flags)
+        _check(L.sph_create(ctypes.byref(prm), n, px, pv, na, py, pu, ctypes.c_void_p(stream), ctypes.byref(out)))
+        self._ctx = out
+
+    @classmethod
+    def batch(cls, per_scene: Sequence[Dict], xs, vs, ys, us, stream: int = 0, flags: int = 0) -> "Simulation":
+        L = lib()
+        S = len(per_scene)
+        prm = (Params * S)(*[params(p, flags) for p in per_scene])
+        poff = np.zeros(S + 1, np.int64)
+        aoff = np.zeros(S + 1, np.int64)
+        poff[1:] = np.cumsum([int(x.shape[0]) for x in xs])
+        aoff[1:] = np.cumsum([int(y.shape[0]) for y in ys])
+        cat = lambda arrs: np.ascontiguousarray(np.concatenate([np.asarray(a, np.float32).reshape(-1, 3) for a in arrs]))  # noqa: E731
+        X, V, Y, U = cat(xs), cat(vs), cat(ys), cat(us)
+        out = ctypes.c_void_p()
+        _check(L.sph_create_batch(prm, S, poff.ctypes.data, aoff.ctypes.data, X.ctypes.data if X.size else None,
+                                  V.ctypes.data if V.size else None, Y.ctypes.data if Y.size else None,
+                                  U.ctypes.data if U.size else None, ctypes.c_void_p(stream), ctypes.byref(out)))
+        sim = cls(None, None, None, None, None, _ctx=out)
+        sim.part_off, sim.agent_off = poff, aoff
+        return sim
+
+    # -- calls ------------------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        _check(lib().sph_step(self._ctx, int(n)), self._ctx)
+
+    def capture(self, n: int) -> None:
+        _check(lib().sph_capture(self._ctx, int(n)), self._ctx)
+
+    def step_profiled(self, n: int) -> Dict[str, float]:
+        """Run n eager steps with HIP events around every kernel; summed ms per kernel."""
+        buf = (ctypes.c_double * STEP_PHASES)()
+        _check(lib().sph_step_profiled(self._ctx, int(n), buf, STEP_PHASES), self._ctx)
+        return {lib().sph_phase_name(p).decode(): buf[p] for p in range(STEP_PHASES)}
+
+    def field_bytes(self, field: int) -> int:
+        b = lib().sph_field_bytes(self._ctx, int(field))
+        if b < 0:
+            _check(int(b), self._ctx)
+        return int(b)
+
+    def read(self, field: int) -> np.ndarray:
+        """Copy a field to a new host numpy array (synchronises the stream)."""
+        dt, w = _FIELD_DTYPE[field]
+        nbytes = self.field_bytes(field)
+        out = np.empty(nbytes // np.dtype(dt).itemsize, dtype=dt)
+        _check(lib().sph_read(self._ctx, int(field), out.ctypes.data if nbytes else None, nbytes), self._ctx)
+        return out.reshape(-1, w) if w > 1 else out
+
+    def read_into(self, field: int, tensor) -> None:
+        """Enqueue a copy of a field into a (device) torch tensor."""
+        nbytes = self.field_bytes(field)
+        if tensor.numel() * tensor.element_size() < nbytes:
+            raise ValueError("tensor too small")
+        _check(lib().sph_read(self._ctx, int(field), ctypes.c_void_p(tensor.data_ptr()),
+                              tensor.numel() * tensor.element_size()), self._ctx)
+
+    def info(self) -> Dict:
+        inf = Info()
+        _check(lib().sph_info_get(self._ctx, ctypes.byref(inf)), self._ctx)
+        return dict(n=inf.n, n_agents=inf.n_agents, dims=tuple(inf.dims), agent_dims=tuple(inf.agent_dims),
+                    cells=inf.cells, agent_cells=inf.agent_cells, cell=inf.cell, agent_cell=inf.agent_cell,
+                    steps=inf.steps, device_bytes=inf.device_bytes)
+
+    def close(self) -> None:
+        if self._ctx:
+            lib().sph_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def create(scene, stream: int = 0, flags: int = 0) -> Simulation:
+    """Simulation of a ``scenes.Scene``."""
+    return Simulation(scene.params, scene.x, scene.v, scene.y, scene.u, stream=stream, flags=flags)
+
+
+def create_batch(scene_list, stream: int = 0, flags: int = 0) -> Simulation:
+    return Simulation.batch([s.params for s in scene_list], [s.x for s in scene_list], [s.v for s in scene_list],
+                            [s.y for s in scene_list], [s.u for s in scene_list], stream=stream, flags=flags)

@@ -1,0 +1,864 @@
+// sph_api.hip -- context, device memory and the C ABI of libsph.so.
+//
+// A context holds one or more independent scenes in one set of SoA arrays
+// (see sph_device.hpp).  A step enqueues, on the context's stream:
+//   sort (fluid and agents of every scene, one batched launch per phase)
+//   -> density -> agents (steering, exact coupling gather, integration)
+//   -> fluid forces + coupling reaction + integration.
+// Nothing is allocated, copied or synchronised inside a step, so a sequence
+// of steps can be captured in a HIP graph and replayed.
+#include <math.h>
+
+#include <cmath>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "sph.h"
+#include "sph_api_internal.hpp"
+#include "sph_device.hpp"
+#include "sph_internal.hpp"
+
+using namespace sph;
+
+static std::string g_create_error;
+
+#define HIPCHK(call)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) {                                            \
+      return fail(ctx, SPH_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    }                                                                  \
+  } while (0)
+
+static sph_status fail(sph_ctx* ctx, sph_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  else g_create_error = buf;
+  return st;
+}
+
+// ------------------------------------------------------------------ setup --
+
+// Cell of edge d = fl32(R (1 + 2^-10)) with R the largest search radius on the
+// grid; inv_d = fl32(1/d); dims = ceil((max - min)/d) in double.  The margin
+// makes the 27-cell stencil contain every pair the single-precision distance
+// test accepts.
+static bool make_grid(const float mn[3], const float mx[3], double r, DGrid& g, float& d, uint64_t& cells) {
+  if (!(r > 0.0)) return false;
+  d = (float)(r * (1.0 + 1.0 / 1024.0));
+  g.inv = (float)(1.0 / (double)d);
+  g.cell = d;
+  cells = 1;
+  for (int k = 0; k < 3; ++k) {
+    double ext = (double)mx[k] - (double)mn[k];
+    if (!(ext > 0.0)) return false;
+    double nd = ceil(ext / (double)d);
+    if (nd < 1.0) nd = 1.0;
+    if (nd > 2147483647.0) return false;
+    g.dim[k] = (int)nd;
+    g.mn[k] = mn[k];
+    cells *= (uint64_t)g.dim[k];
+  }
+  g.ncells = (uint32_t)std::min<uint64_t>(cells, 0xFFFFFFFFull);
+  return true;
+}
+
+// Pair-term constants (Section "Pressure and Viscosity"): the combined term is
+// (m/rho_j)(1-q)[Cp k (rho_i + rho_j - 2 rho0)(1-q) r_ij/q - Cv mu v_ij].
+// kernel_norm 0: 3-D normalised spiky gradient and viscosity Laplacian,
+// Cp = 45/(2 pi R^5), Cv = 45/(pi R^5); 1: the printed 15/(pi R^4), 40/(pi R^4).
+static void pair_constants(int norm, double R, double& cp, double& cv) {
+  const double pi = 3.14159265358979323846;
+  if (norm == 1) {
+    cp = 15.0 / (pi * R * R * R * R);
+    cv = 40.0 / (pi * R * R * R * R);
+  } else {
+    cp = 45.0 / (2.0 * pi * R * R * R * R * R);
+    cv = 45.0 / (pi * R * R * R * R * R);
+  }
+}
+
+static sph_status derive_scene(const sph_params& p, int64_t n, int64_t na, DScene& S, std::string& why) {
+  char buf[256];
+  auto bad = [&](const char* m) {
+    why = m;
+    return SPH_EINVAL;
+  };
+  if (!(p.h > 0.0f) || !std::isfinite(p.h)) return bad("h must be positive and finite");
+  if (!(p.mass > 0.0f)) return bad("mass must be positive");
+  if (!(p.rest_density > 0.0f)) return bad("rest_density must be positive");
+  if (!(p.dt >= 0.0f) || !std::isfinite(p.dt)) return bad("dt must be >= 0");
+  if (!(p.r_couple > 0.0f) || !(p.r_sep >= 0.0f) || !(p.r_ali >= 0.0f) || !(p.r_coh >= 0.0f))
+    return bad("boid radii must be >= 0 and r_couple > 0");
+  if (p.kernel_norm != 0 && p.kernel_norm != 1) return bad("kernel_norm must be 0 or 1");
+  if (!(p.v_min >= 0.0f) || !(p.v_max >= p.v_min)) return bad("need 0 <= v_min <= v_max");
+  for (int k = 0; k < 3; ++k)
+    if (!(p.box_max[k] > p.box_min[k]) || !std::isfinite(p.box_min[k]) || !std::isfinite(p.box_max[k]))
+      return bad("box_max must exceed box_min on every axis");
+  if (n < 0 || na < 0 || n >= (1ll << 31) || na >= (1ll << 31)) return bad("particle / agent count out of range");
+  float d, da;
+  uint64_t cells, acells;
+  if (!make_grid(p.box_min, p.box_max, (double)p.h, S.g, d, cells)) return bad("invalid fluid grid");
+  double ra = std::max(std::max((double)p.r_sep, (double)p.r_ali), std::max((double)p.r_coh, (double)p.r_couple));
+  if (!make_grid(p.box_min, p.box_max, ra, S.ga, da, acells)) return bad("invalid agent grid");
+  if (cells >= (1ull << 31) || acells >= (1ull << 31) || (p.n_buckets && cells > p.n_buckets)) {
+    snprintf(buf, sizeof buf, "grid of %llu cells exceeds the cell table (n_buckets = %u)",
+             (unsigned long long)cells, p.n_buckets);
+    why = buf;
+    return SPH_ECAPACITY;
+  }
+  S.n = (uint32_t)n;
+  S.na = (uint32_t)na;
+  S.ns_c = std::max(1, (int)ceil((double)p.r_couple / (double)d));
+  const double h = p.h, m = p.mass, k = p.gas_k, mu = p.viscosity, rho0 = p.rest_density;
+  const double pi = 3.14159265358979323846;
+  S.h2 = (float)(h * h);
+  S.inv_h = (float)(1.0 / h);
+  S.c6m = (float)(m * 315.0 / (64.0 * pi * pow(h, 9)));
+  S.rho0 = p.rest_density;
+  double cp, cv;
+  pair_constants(p.kernel_norm, h, cp, cv);
+  S.cpk_h = (float)(cp * k * h);
+  S.cvmu = (float)(cv * mu);
+  S.m = p.mass;
+  S.inv_m = (float)(1.0 / m);
+  S.dt = p.dt;
+  S.e = p.wall_restitution;
+  for (int a = 0; a < 3; ++a) {
+    S.grav[a] = p.gravity[a];
+    S.bmin[a] = p.box_min[a];
+    S.bmax[a] = p.box_max[a];
+  }
+  const double rc = p.r_couple;
+  S.rc2 = (float)(rc * rc);
+  S.inv_rc = (float)(1.0 / rc);
+  pair_constants(p.kernel_norm, rc, cp, cv);
+  S.cpk_hc = (float)(cp * k * rc);
+  S.cvmu_c = (float)(cv * mu);
+  S.m_over_rho0 = (float)(m / rho0);
+  S.cf = p.couple_factor;
+  S.rsep2 = (float)((double)p.r_sep * (double)p.r_sep);
+  S.rali2 = (float)((double)p.r_ali * (double)p.r_ali);
+  S.rcoh2 = (float)((double)p.r_coh * (double)p.r_coh);
+  S.inv_rsep = p.r_sep > 0.0f ? (float)(1.0 / (double)p.r_sep) : 0.0f;
+  S.wsep = p.w_sep;
+  S.wali = p.w_ali;
+  S.wcoh = p.w_coh;
+  S.vmin = p.v_min;
+  S.vmax = p.v_max;
+  return SPH_OK;
+}
+
+__global__ void k_split_aos(const float* __restrict__ aos, uint32_t n, float* __restrict__ x, float* __restrict__ y,
+                            float* __restrict__ z) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = aos[3 * (size_t)i + 0];
+  y[i] = aos[3 * (size_t)i + 1];
+  z[i] = aos[3 * (size_t)i + 2];
+}
+
+__global__ void k_local_iota(const uint32_t* __restrict__ prefix, int nsets, uint32_t total, uint32_t* __restrict__ out) {
+  uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= total) return;
+  int s = find_set(prefix, nsets, gi);
+  out[gi] = gi - prefix[s];
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves typed arrays out of one device allocation.
+struct Arena {
+  std::vector<std::pair<void**, size_t>> req;
+  template <class T>
+  void add(T*& p, size_t count) {
+    req.push_back({(void**)&p, align_up(std::max<size_t>(count, 1) * sizeof(T), 256)});
+  }
+  size_t total() const {
+    size_t t = 0;
+    for (auto& r : req) t += r.second;
+    return t;
+  }
+  void bind(char* base) {
+    size_t o = 0;
+    for (auto& r : req) {
+      *r.first = base + o;
+      o += r.second;
+    }
+  }
+};
+
+sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vector<int64_t>& n,
+                         const std::vector<int64_t>& na, const std::vector<const float*>& pos,
+                         const std::vector<const float*>& vel, const std::vector<const float*>& apos,
+                         const std::vector<const float*>& avel, void* stream, sph_ctx** out) {
+  sph_ctx* ctx = nullptr;
+  const int S = (int)params.size();
+  if (S <= 0) return fail(nullptr, SPH_EINVAL, "no scenes");
+  std::vector<DScene> hs(S);
+  uint64_t N = 0, A = 0, C = 0, AC = 0;
+  for (int s = 0; s < S; ++s) {
+    std::string why;
+    memset(&hs[s], 0, sizeof(DScene));
+    sph_status st = derive_scene(params[s], n[s], na[s], hs[s], why);
+    if (st != SPH_OK) return fail(nullptr, st, "scene %d: %s", s, why.c_str());
+    if ((n[s] > 0 && (!pos[s] || !vel[s])) || (na[s] > 0 && (!apos[s] || !avel[s])))
+      return fail(nullptr, SPH_EINVAL, "scene %d: NULL state pointer", s);
+    hs[s].pbase = (uint32_t)N;
+    hs[s].abase = (uint32_t)A;
+    hs[s].cbase = (uint32_t)C;
+    hs[s].obase = (uint32_t)(C + s);
+    hs[s].acbase = (uint32_t)AC;
+    hs[s].aobase = (uint32_t)(AC + s);
+    N += n[s];
+    A += na[s];
+    C += hs[s].g.ncells;
+    AC += hs[s].ga.ncells;
+    if (N >= (1ull << 31) || A >= (1ull << 31) || C + S >= (1ull << 31) || AC + S >= (1ull << 31))
+      return fail(nullptr, SPH_ECAPACITY, "total size exceeds 2^31 elements");
+  }
+  ctx = new sph_ctx();
+  ctx->nscenes = S;
+  ctx->hs = hs;
+  ctx->params = params;
+  ctx->N = (uint32_t)N;
+  ctx->A = (uint32_t)A;
+  ctx->C = (uint32_t)C;
+  ctx->AC = (uint32_t)AC;
+  ctx->diag = (params[0].flags & SPH_FLAG_DIAGNOSTICS) != 0;
+  ctx->check_finite = (params[0].flags & SPH_FLAG_CHECK_FINITE) != 0;
+  ctx->stream = (hipStream_t)stream;
+
+  // sort sets: fluid of every scene, then agents of every scene
+  const int nsets = 2 * S;
+  std::vector<uint32_t> prefix(nsets + 1, 0), chunk_prefix(nsets + 1, 0);
+  for (int t = 0; t < nsets; ++t) {
+    const DScene& d = hs[t % S];
+    const bool ag = t >= S;
+    prefix[t + 1] = prefix[t] + (ag ? d.na : d.n);
+    chunk_prefix[t + 1] = chunk_prefix[t] + scan_chunks(ag ? d.ga.ncells : d.g.ncells);
+  }
+  ctx->nsets = nsets;
+  ctx->nchunks = chunk_prefix[nsets];
+  // tile width and kernel variant (SPH_TILE_X, SPH_FLUID_VARIANT override the defaults)
+  int tx = 16, variant = 0;
+  if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(kTXMax, atoi(e)));
+  if (const char* e = getenv("SPH_FLUID_VARIANT")) variant = std::max(0, std::min(fluid_variants() - 1, atoi(e)));
+  std::vector<uint32_t> tprefix(S + 1, 0);
+  for (int s = 0; s < S; ++s) {
+    const uint64_t t = (uint64_t)tprefix[s] + fluid_tiles(hs[s].g, 1);
+    if (t >= (1ull << 31)) return fail(nullptr, SPH_ECAPACITY, "too many fluid tiles");
+    tprefix[s + 1] = (uint32_t)t;
+  }
+  std::vector<uint32_t> fprefix(S + 1), aprefix(S + 1);
+  for (int s = 0; s <= S; ++s) {
+    fprefix[s] = prefix[s];
+    aprefix[s] = prefix[S + s] - prefix[S];
+  }
+
+  Arena ar;
+  ar.add(ctx->px, N); ar.add(ctx->py, N); ar.add(ctx->pz, N);
+  ar.add(ctx->vx, N); ar.add(ctx->vy, N); ar.add(ctx->vz, N);
+  ar.add(ctx->sx, N); ar.add(ctx->sy, N); ar.add(ctx->sz, N);
+  ar.add(ctx->svx, N); ar.add(ctx->svy, N); ar.add(ctx->svz, N);
+  ar.add(ctx->sid, N); ar.add(ctx->key, N); ar.add(ctx->rank, N); ar.add(ctx->tsrc, N); ar.add(ctx->tid, N);
+  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * N);
+  ar.add(ctx->cnt, C); ar.add(ctx->off, C + S);
+  ar.add(ctx->agx, A); ar.add(ctx->agy, A); ar.add(ctx->agz, A);
+  ar.add(ctx->aux, A); ar.add(ctx->auy, A); ar.add(ctx->auz, A);
+  ar.add(ctx->asx, A); ar.add(ctx->asy, A); ar.add(ctx->asz, A);
+  ar.add(ctx->asvx, A); ar.add(ctx->asvy, A); ar.add(ctx->asvz, A);
+  ar.add(ctx->asid, A); ar.add(ctx->aiota, A); ar.add(ctx->akey, A); ar.add(ctx->arank, A);
+  ar.add(ctx->atsrc, A); ar.add(ctx->atid, A);
+  ar.add(ctx->acnt, AC); ar.add(ctx->aoff, AC + S);
+  if (ctx->diag) {
+    ar.add(ctx->d_aint, 3 * N); ar.add(ctx->d_acoup, 3 * N); ar.add(ctx->d_touch, N);
+    ar.add(ctx->d_steer, 3 * A); ar.add(ctx->d_force, 3 * A); ar.add(ctx->d_acnt, 4 * A);
+  }
+  ar.add(ctx->bsum, ctx->nchunks);
+  ar.add(ctx->d_sets, nsets);
+  ar.add(ctx->d_prefix, nsets + 1);
+  ar.add(ctx->d_chunk_prefix, nsets + 1);
+  ar.add(ctx->d_scenes, S);
+  ar.add(ctx->d_fprefix, S + 1);
+  ar.add(ctx->d_aprefix, S + 1);
+  ar.add(ctx->d_pairs, 1);
+  ar.add(ctx->d_tprefix, S + 1);
+  ar.add(ctx->d_counters, kWorkCounters);
+  ar.add(ctx->d_tile_list, tprefix[S]);
+  ar.add(ctx->d_flag, 1);
+  ctx->bytes = ar.total();
+  hipError_t e = hipMalloc((void**)&ctx->arena, ctx->bytes);
+  if (e != hipSuccess) {
+    const size_t want = ctx->bytes;
+    delete ctx;
+    return fail(nullptr, SPH_ENOMEM, "hipMalloc of %zu bytes failed: %s", want, hipGetErrorString(e));
+  }
+  ar.bind(ctx->arena);
+
+  auto bail = [&](sph_status st) {
+    g_create_error = ctx->err;
+    sph_destroy(ctx);
+    return st;
+  };
+#define CHK(call)                                                               \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      fail(ctx, SPH_EHIP, "%s: %s", #call, hipGetErrorString(e_));              \
+      return bail(SPH_EHIP);                                                    \
+    }                                                                           \
+  } while (0)
+
+  hipStream_t st = ctx->stream;
+  CHK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+  // tables
+  std::vector<SortSet> sets(nsets);
+  for (int t = 0; t < nsets; ++t) {
+    const DScene& d = hs[t % S];
+    SortSet& q = sets[t];
+    memset(&q, 0, sizeof q);
+    if (t < S) {
+      const uint32_t b = d.pbase;
+      q.x = ctx->px + b; q.y = ctx->py + b; q.z = ctx->pz + b;
+      q.vx = ctx->vx + b; q.vy = ctx->vy + b; q.vz = ctx->vz + b;
+      q.id = ctx->sid + b;
+      q.sx = ctx->sx + b; q.sy = ctx->sy + b; q.sz = ctx->sz + b;
+      q.svx = ctx->svx + b; q.svy = ctx->svy + b; q.svz = ctx->svz + b;
+      q.sid = ctx->sid + b;
+      q.key = ctx->key + b; q.rank = ctx->rank + b; q.tsrc = ctx->tsrc + b; q.tid = ctx->tid + b;
+      q.cnt = ctx->cnt + d.cbase; q.off = ctx->off + d.obase;
+      q.g = d.g;
+      q.n = d.n;
+    } else {
+      const uint32_t b = d.abase;
+      q.x = ctx->agx + b; q.y = ctx->agy + b; q.z = ctx->agz + b;
+      q.vx = ctx->aux + b; q.vy = ctx->auy + b; q.vz = ctx->auz + b;
+      q.id = ctx->aiota + b;
+      q.sx = ctx->asx + b; q.sy = ctx->asy + b; q.sz = ctx->asz + b;
+      q.svx = ctx->asvx + b; q.svy = ctx->asvy + b; q.svz = ctx->asvz + b;
+      q.sid = ctx->asid + b;
+      q.key = ctx->akey + b; q.rank = ctx->arank + b; q.tsrc = ctx->atsrc + b; q.tid = ctx->atid + b;
+      q.cnt = ctx->acnt + d.acbase; q.off = ctx->aoff + d.aobase;
+      q.g = d.ga;
+      q.n = d.na;
+    }
+  }
+  CHK(hipMemcpyAsync(ctx->d_sets, sets.data(), sizeof(SortSet) * nsets, hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(ctx->d_prefix, prefix.data(), 4 * (nsets + 1), hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(ctx->d_chunk_prefix, chunk_prefix.data(), 4 * (nsets + 1), hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(ctx->d_scenes, hs.data(), sizeof(DScene) * S, hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(ctx->d_fprefix, fprefix.data(), 4 * (S + 1), hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(ctx->d_aprefix, aprefix.data(), 4 * (S + 1), hipMemcpyHostToDevice, st));
+  CHK(hipMemsetAsync(ctx->d_counters, 0, 4 * kWorkCounters, st));
+  CHK(hipMemsetAsync(ctx->cnt, 0, 4 * std::max<uint64_t>(C, 1), st));
+  CHK(hipMemsetAsync(ctx->acnt, 0, 4 * std::max<uint64_t>(AC, 1), st));
+  CHK(hipMemsetAsync(ctx->off, 0, 4 * (C + S), st));
+  CHK(hipMemsetAsync(ctx->aoff, 0, 4 * (AC + S), st));
+  CHK(hipMemsetAsync(ctx->rho, 0, 4 * std::max<uint64_t>(N, 1), st));
+  CHK(hipMemsetAsync(ctx->nbr, 0, 4 * std::max<uint64_t>(N, 1), st));
+  CHK(hipMemsetAsync(ctx->d_pairs, 0, 8, st));
+  if (ctx->diag) {
+    CHK(hipMemsetAsync(ctx->d_aint, 0, 12 * std::max<uint64_t>(N, 1), st));
+    CHK(hipMemsetAsync(ctx->d_acoup, 0, 12 * std::max<uint64_t>(N, 1), st));
+    CHK(hipMemsetAsync(ctx->d_touch, 0, 4 * std::max<uint64_t>(N, 1), st));
+    CHK(hipMemsetAsync(ctx->d_steer, 0, 12 * std::max<uint64_t>(A, 1), st));
+    CHK(hipMemsetAsync(ctx->d_force, 0, 12 * std::max<uint64_t>(A, 1), st));
+    CHK(hipMemsetAsync(ctx->d_acnt, 0, 16 * std::max<uint64_t>(A, 1), st));
+  }
+  // ids: local iota per scene (fluid storage order starts as id order)
+  if (N) hipLaunchKernelGGL(k_local_iota, dim3((N + 255) / 256), dim3(256), 0, st, ctx->d_fprefix, S, (uint32_t)N, ctx->sid);
+  if (A) {
+    hipLaunchKernelGGL(k_local_iota, dim3((A + 255) / 256), dim3(256), 0, st, ctx->d_aprefix, S, (uint32_t)A, ctx->aiota);
+    CHK(hipMemcpyAsync(ctx->asid, ctx->aiota, 4 * A, hipMemcpyDeviceToDevice, st));
+  }
+  // state: AoS inputs (host or device) -> staging -> SoA
+  uint64_t stage = 3 * std::max<uint64_t>(std::max(N, A), 1);
+  float* staging = nullptr;
+  CHK(hipMalloc((void**)&staging, 4 * stage));
+  auto upload = [&](const std::vector<const float*>& src, const std::vector<int64_t>& cnt,
+                    const std::vector<uint32_t>& base, uint32_t total, float* x, float* y, float* z) -> hipError_t {
+    for (int s = 0; s < S; ++s) {
+      if (cnt[s] == 0) continue;
+      hipError_t e2 = hipMemcpyAsync(staging + 3 * (size_t)base[s], src[s], 12 * (size_t)cnt[s], hipMemcpyDefault, st);
+      if (e2 != hipSuccess) return e2;
+    }
+    if (total) hipLaunchKernelGGL(k_split_aos, dim3((total + 255) / 256), dim3(256), 0, st, staging, total, x, y, z);
+    return hipStreamSynchronize(st);
+  };
+  std::vector<uint32_t> pb(S), ab(S);
+  for (int s = 0; s < S; ++s) {
+    pb[s] = hs[s].pbase;
+    ab[s] = hs[s].abase;
+  }
+  hipError_t ue = upload(pos, n, pb, ctx->N, ctx->px, ctx->py, ctx->pz);
+  if (ue == hipSuccess) ue = upload(vel, n, pb, ctx->N, ctx->vx, ctx->vy, ctx->vz);
+  if (ue == hipSuccess) ue = upload(apos, na, ab, ctx->A, ctx->agx, ctx->agy, ctx->agz);
+  if (ue == hipSuccess) ue = upload(avel, na, ab, ctx->A, ctx->aux, ctx->auy, ctx->auz);
+  (void)hipFree(staging);
+  if (ue != hipSuccess) {
+    fail(ctx, SPH_EHIP, "state upload: %s", hipGetErrorString(ue));
+    return bail(SPH_EHIP);
+  }
+  CHK(hipGetLastError());
+
+  ctx->sort.sets = ctx->d_sets;
+  ctx->sort.nsets = nsets;
+  ctx->sort.prefix = ctx->d_prefix;
+  ctx->sort.total = prefix[nsets];
+  ctx->sort.chunk_prefix = ctx->d_chunk_prefix;
+  ctx->sort.nchunks = ctx->nchunks;
+  ctx->sort.bsum = ctx->bsum;
+  ctx->sort.counters = ctx->d_counters;
+  ctx->ntiles = tprefix[S];
+
+  PhysPlan& P = ctx->phys;
+  memset(&P, 0, sizeof P);
+  P.scenes = ctx->d_scenes;
+  P.nscenes = S;
+  P.fprefix = ctx->d_fprefix;
+  P.nf = ctx->N;
+  P.aprefix = ctx->d_aprefix;
+  P.na = ctx->A;
+  P.sx = ctx->sx; P.sy = ctx->sy; P.sz = ctx->sz;
+  P.svx = ctx->svx; P.svy = ctx->svy; P.svz = ctx->svz;
+  P.off = ctx->off;
+  P.rho = ctx->rho;
+  P.nbr = ctx->nbr;
+  P.nmask = ctx->nmask;
+  P.pairs = ctx->d_pairs;
+  P.tprefix = ctx->d_tprefix;
+  P.ntiles = tprefix[S];
+  P.tile_list = ctx->d_tile_list;
+  P.tx = tx;
+  P.variant = variant;
+  if (set_tiling(ctx, tx, variant) != SPH_OK) return bail(SPH_EHIP);
+  P.counters = ctx->d_counters;
+  P.px = ctx->px; P.py = ctx->py; P.pz = ctx->pz;
+  P.vx = ctx->vx; P.vy = ctx->vy; P.vz = ctx->vz;
+  P.agx = ctx->agx; P.agy = ctx->agy; P.agz = ctx->agz;
+  P.aux = ctx->aux; P.auy = ctx->auy; P.auz = ctx->auz;
+  P.asx = ctx->asx; P.asy = ctx->asy; P.asz = ctx->asz;
+  P.asvx = ctx->asvx; P.asvy = ctx->asvy; P.asvz = ctx->asvz;
+  P.asid = ctx->asid;
+  P.aoff = ctx->aoff;
+  if (ctx->diag) {
+    P.d_aint = ctx->d_aint; P.d_acoup = ctx->d_acoup; P.d_touch = ctx->d_touch;
+    P.d_steer = ctx->d_steer; P.d_force = ctx->d_force; P.d_acnt = ctx->d_acnt;
+  }
+  *out = ctx;
+#undef CHK
+  return SPH_OK;
+}
+
+// Tile width and kernel variant of the fluid passes.  The tile list is sized
+// for one-cell tiles, so any width fits.
+sph_status set_tiling(sph_ctx* ctx, int tx, int variant) {
+  if (tx < 1 || tx > kTXMax || variant < 0 || variant >= fluid_variants())
+    return fail(ctx, SPH_EINVAL, "tile width must be in [1, %d] and variant in [0, %d)", kTXMax, fluid_variants());
+  std::vector<uint32_t> tp(ctx->nscenes + 1, 0);
+  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx);
+  // ordered after every kernel already enqueued on the stream that reads the old prefix
+  hipError_t e = hipMemcpyAsync(ctx->d_tprefix, tp.data(), 4 * tp.size(), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, SPH_EHIP, "tile prefix upload: %s", hipGetErrorString(e));
+  ctx->phys.ntiles = tp[ctx->nscenes];
+  ctx->phys.tx = tx;
+  ctx->phys.variant = variant;
+  return SPH_OK;
+}
+
+// ------------------------------------------------------------------- step --
+
+sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
+  for (int32_t k = 0; k < n_steps; ++k) {
+    launch_sort(ctx->sort, st);
+    launch_density(ctx->phys, st);
+    launch_agents(ctx->phys, st);
+    launch_force(ctx->phys, st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, SPH_EHIP, "kernel launch: %s", hipGetErrorString(e));
+  return SPH_OK;
+}
+
+// Phase p of one step (p < kStepPhases), in launch order.
+static void launch_phase(sph_ctx* ctx, int p, hipStream_t st) {
+  if (p < kSortPhases) launch_sort_phase(ctx->sort, p, st);
+  else if (p == kSortPhases) launch_density(ctx->phys, st);
+  else if (p == kSortPhases + 1) launch_agents(ctx->phys, st);
+  else launch_force(ctx->phys, st);
+}
+
+sph_status sph_profile_impl(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases) {
+  if (n_phases < kStepPhases) return fail(ctx, SPH_EINVAL, "phase_ms must hold %d entries", kStepPhases);
+  for (int p = 0; p < n_phases; ++p) phase_ms[p] = 0.0;
+  if (n_steps <= 0) return SPH_OK;
+  hipStream_t st = ctx->stream;
+  const int ne = n_steps * kStepPhases + 1;
+  std::vector<hipEvent_t> ev(ne, nullptr);
+  sph_status status = SPH_OK;
+  for (int k = 0; k < ne; ++k) {
+    if (hipEventCreate(&ev[k]) != hipSuccess) {
+      status = fail(ctx, SPH_EHIP, "hipEventCreate failed");
+      break;
+    }
+  }
+  if (status == SPH_OK) {
+    int e = 0;
+    hipError_t he = hipEventRecord(ev[e++], st);
+    for (int s = 0; s < n_steps && he == hipSuccess; ++s)
+      for (int p = 0; p < kStepPhases && he == hipSuccess; ++p) {
+        launch_phase(ctx, p, st);
+        he = hipEventRecord(ev[e++], st);
+      }
+    if (he == hipSuccess) he = hipGetLastError();
+    if (he == hipSuccess) he = hipEventSynchronize(ev[ne - 1]);
+    if (he != hipSuccess) status = fail(ctx, SPH_EHIP, "profiled step: %s", hipGetErrorString(he));
+    for (int s = 0; s < n_steps && status == SPH_OK; ++s)
+      for (int p = 0; p < kStepPhases; ++p) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[s * kStepPhases + p], ev[s * kStepPhases + p + 1]) != hipSuccess) {
+          status = fail(ctx, SPH_EHIP, "hipEventElapsedTime failed");
+          break;
+        }
+        phase_ms[p] += ms;
+      }
+    if (status == SPH_OK) ctx->steps += n_steps;
+  }
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return status;
+}
+
+__global__ void k_check_finite(const float* __restrict__ a, uint32_t n, int* flag) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(a[i])) atomicOr(flag, 1);
+}
+
+static sph_status check_finite(sph_ctx* ctx) {
+  hipStream_t st = ctx->stream;
+  HIPCHK(hipMemsetAsync(ctx->d_flag, 0, 4, st));
+  const float* arrs[12] = {ctx->px, ctx->py, ctx->pz, ctx->vx, ctx->vy, ctx->vz,
+                           ctx->agx, ctx->agy, ctx->agz, ctx->aux, ctx->auy, ctx->auz};
+  for (int k = 0; k < 12; ++k) {
+    uint32_t n = k < 6 ? ctx->N : ctx->A;
+    if (n) hipLaunchKernelGGL(k_check_finite, dim3((n + 255) / 256), dim3(256), 0, st, arrs[k], n, ctx->d_flag);
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (flag) return fail(ctx, SPH_ENONFINITE, "non-finite position or velocity in the state");
+  return SPH_OK;
+}
+
+// ------------------------------------------------------------------- read --
+
+__global__ void k_out_fluid_soa(const DScene* __restrict__ sc, const uint32_t* __restrict__ fprefix, int ns,
+                                uint32_t n, const uint32_t* __restrict__ sid, const float* __restrict__ a,
+                                const float* __restrict__ b, const float* __restrict__ c, float* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = find_set(fprefix, ns, i);
+  size_t o = 3 * ((size_t)fprefix[s] + sid[i]);
+  out[o] = a[i];
+  out[o + 1] = b[i];
+  out[o + 2] = c[i];
+}
+
+__global__ void k_out_fluid_vec(const uint32_t* __restrict__ fprefix, int ns, uint32_t n, const uint32_t* __restrict__ sid,
+                                const float* __restrict__ a, float* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = find_set(fprefix, ns, i);
+  size_t o = 3 * ((size_t)fprefix[s] + sid[i]);
+  out[o] = a[3 * (size_t)i];
+  out[o + 1] = a[3 * (size_t)i + 1];
+  out[o + 2] = a[3 * (size_t)i + 2];
+}
+
+__global__ void k_out_fluid_scalar(const uint32_t* __restrict__ fprefix, int ns, uint32_t n,
+                                   const uint32_t* __restrict__ sid, const uint32_t* __restrict__ a,
+                                   uint32_t* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = find_set(fprefix, ns, i);
+  out[fprefix[s] + sid[i]] = a[i];
+}
+
+// Cell key of sorted slot i: the cell c with off[c] <= slot < off[c + 1].
+__global__ void k_out_fluid_key(const DScene* __restrict__ sc, const uint32_t* __restrict__ fprefix, int ns, uint32_t n,
+                                const uint32_t* __restrict__ sid, const uint32_t* __restrict__ off,
+                                uint32_t* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = find_set(fprefix, ns, i);
+  const uint32_t slot = i - fprefix[s];
+  const uint32_t* o = off + sc[s].obase;
+  uint32_t lo = 0, hi = sc[s].g.ncells - 1;
+  while (lo < hi) {
+    uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (o[mid] <= slot) lo = mid;
+    else hi = mid - 1;
+  }
+  out[fprefix[s] + sid[i]] = lo;
+}
+
+__global__ void k_out_soa(uint32_t n, const float* __restrict__ a, const float* __restrict__ b,
+                          const float* __restrict__ c, float* __restrict__ out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[3 * (size_t)i] = a[i];
+  out[3 * (size_t)i + 1] = b[i];
+  out[3 * (size_t)i + 2] = c[i];
+}
+
+int64_t field_bytes(const sph_ctx* ctx, int32_t f) {
+  const int64_t N = ctx->N, A = ctx->A;
+  switch (f) {
+    case SPH_POS: case SPH_VEL: case SPH_ACC_INT: case SPH_ACC_COUPLE: return 12 * N;
+    case SPH_AGENT_POS: case SPH_AGENT_VEL: case SPH_AGENT_FORCE: case SPH_AGENT_STEER: return 12 * A;
+    case SPH_DENSITY: case SPH_NBR_COUNT: case SPH_CELL_KEY: case SPH_TOUCHED: case SPH_SORTED_IDS: return 4 * N;
+    case SPH_AGENT_COUNTS: return 16 * A;
+    case SPH_CELL_OFFSETS: return 4 * ((int64_t)ctx->C + ctx->nscenes);
+    case SPH_AGENT_KEY: case SPH_AGENT_SORTED_IDS: return 4 * A;
+    case SPH_AGENT_CELL_OFFSETS: return 4 * ((int64_t)ctx->AC + ctx->nscenes);
+    case SPH_PAIR_COUNT: return 8;
+    default: return -1;
+  }
+}
+
+sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_bytes) {
+  int64_t need = field_bytes(ctx, field);
+  if (need < 0) return fail(ctx, SPH_EINVAL, "unknown field %d", field);
+  if (!dst && need > 0) return fail(ctx, SPH_EINVAL, "NULL destination");
+  if (dst_bytes < need) return fail(ctx, SPH_EINVAL, "destination holds %lld bytes, field needs %lld",
+                                    (long long)dst_bytes, (long long)need);
+  const bool is_diag = field == SPH_ACC_INT || field == SPH_ACC_COUPLE || field == SPH_TOUCHED ||
+                       field == SPH_AGENT_FORCE || field == SPH_AGENT_STEER || field == SPH_AGENT_COUNTS;
+  if (is_diag && !ctx->diag) return fail(ctx, SPH_ESTATE, "diagnostics were not enabled (SPH_FLAG_DIAGNOSTICS)");
+  if (need == 0) return SPH_OK;
+  hipStream_t st = ctx->stream;
+  if (!ctx->staging || ctx->staging_bytes < (size_t)need) {
+    if (ctx->staging) HIPCHK(hipFree(ctx->staging));
+    ctx->staging = nullptr;
+    HIPCHK(hipMalloc(&ctx->staging, (size_t)need));
+    ctx->staging_bytes = (size_t)need;
+  }
+  void* out = ctx->staging;
+  const uint32_t N = ctx->N, A = ctx->A;
+  const dim3 bn((N + 255) / 256), ba((A + 255) / 256), b256(256);
+  const int S = ctx->nscenes;
+  switch (field) {
+    case SPH_POS:
+      hipLaunchKernelGGL(k_out_fluid_soa, bn, b256, 0, st, ctx->d_scenes, ctx->d_fprefix, S, N, ctx->sid, ctx->px, ctx->py, ctx->pz, (float*)out);
+      break;
+    case SPH_VEL:
+      hipLaunchKernelGGL(k_out_fluid_soa, bn, b256, 0, st, ctx->d_scenes, ctx->d_fprefix, S, N, ctx->sid, ctx->vx, ctx->vy, ctx->vz, (float*)out);
+      break;
+    case SPH_ACC_INT:
+      hipLaunchKernelGGL(k_out_fluid_vec, bn, b256, 0, st, ctx->d_fprefix, S, N, ctx->sid, ctx->d_aint, (float*)out);
+      break;
+    case SPH_ACC_COUPLE:
+      hipLaunchKernelGGL(k_out_fluid_vec, bn, b256, 0, st, ctx->d_fprefix, S, N, ctx->sid, ctx->d_acoup, (float*)out);
+      break;
+    case SPH_DENSITY:
+      hipLaunchKernelGGL(k_out_fluid_scalar, bn, b256, 0, st, ctx->d_fprefix, S, N, ctx->sid, (const uint32_t*)ctx->rho, (uint32_t*)out);
+      break;
+    case SPH_NBR_COUNT:
+      hipLaunchKernelGGL(k_out_fluid_scalar, bn, b256, 0, st, ctx->d_fprefix, S, N, ctx->sid, ctx->nbr, (uint32_t*)out);
+      break;
+    case SPH_TOUCHED:
+      hipLaunchKernelGGL(k_out_fluid_scalar, bn, b256, 0, st, ctx->d_fprefix, S, N, ctx->sid, ctx->d_touch, (uint32_t*)out);
+      break;
+    case SPH_CELL_KEY:
+      hipLaunchKernelGGL(k_out_fluid_key, bn, b256, 0, st, ctx->d_scenes, ctx->d_fprefix, S, N, ctx->sid, ctx->off, (uint32_t*)out);
+      break;
+    case SPH_SORTED_IDS:
+      HIPCHK(hipMemcpyAsync(out, ctx->sid, 4 * (size_t)N, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_CELL_OFFSETS:
+      HIPCHK(hipMemcpyAsync(out, ctx->off, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_POS:
+      hipLaunchKernelGGL(k_out_soa, ba, b256, 0, st, A, ctx->agx, ctx->agy, ctx->agz, (float*)out);
+      break;
+    case SPH_AGENT_VEL:
+      hipLaunchKernelGGL(k_out_soa, ba, b256, 0, st, A, ctx->aux, ctx->auy, ctx->auz, (float*)out);
+      break;
+    case SPH_AGENT_FORCE:
+      HIPCHK(hipMemcpyAsync(out, ctx->d_force, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_STEER:
+      HIPCHK(hipMemcpyAsync(out, ctx->d_steer, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_COUNTS:
+      HIPCHK(hipMemcpyAsync(out, ctx->d_acnt, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_KEY:
+      HIPCHK(hipMemcpyAsync(out, ctx->akey, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_SORTED_IDS:
+      HIPCHK(hipMemcpyAsync(out, ctx->asid, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_CELL_OFFSETS:
+      HIPCHK(hipMemcpyAsync(out, ctx->aoff, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_PAIR_COUNT:
+      HIPCHK(hipMemcpyAsync(out, ctx->d_pairs, 8, hipMemcpyDeviceToDevice, st));
+      break;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(dst, out, (size_t)need, hipMemcpyDefault, st));
+  hipPointerAttribute_t attr;
+  bool device_dst = hipPointerGetAttributes(&attr, dst) == hipSuccess && attr.type == hipMemoryTypeDevice;
+  (void)hipGetLastError();
+  if (!device_dst) HIPCHK(hipStreamSynchronize(st));
+  return SPH_OK;
+}
+
+// -------------------------------------------------------------------- ABI --
+
+extern "C" {
+
+sph_status sph_create(const sph_params* params, int64_t n, const float* pos, const float* vel, int64_t n_agents,
+                      const float* agent_pos, const float* agent_vel, void* hip_stream, sph_ctx** out) {
+  if (!params || !out) return fail(nullptr, SPH_EINVAL, "NULL params or out");
+  *out = nullptr;
+  return sph_ctx_build({*params}, {n}, {n_agents}, {pos}, {vel}, {agent_pos}, {agent_vel}, hip_stream, out);
+}
+
+sph_status sph_create_batch(const sph_params* per_scene, int32_t n_scenes, const int64_t* part_off,
+                            const int64_t* agent_off, const float* pos, const float* vel, const float* agent_pos,
+                            const float* agent_vel, void* hip_stream, sph_ctx** out) {
+  if (!per_scene || !out || !part_off || !agent_off || n_scenes <= 0)
+    return fail(nullptr, SPH_EINVAL, "NULL argument or n_scenes <= 0");
+  *out = nullptr;
+  if (part_off[0] != 0 || agent_off[0] != 0) return fail(nullptr, SPH_EINVAL, "offsets must start at 0");
+  std::vector<sph_params> ps(per_scene, per_scene + n_scenes);
+  std::vector<int64_t> n(n_scenes), na(n_scenes);
+  std::vector<const float*> x(n_scenes), v(n_scenes), y(n_scenes), u(n_scenes);
+  for (int s = 0; s < n_scenes; ++s) {
+    n[s] = part_off[s + 1] - part_off[s];
+    na[s] = agent_off[s + 1] - agent_off[s];
+    if (n[s] < 0 || na[s] < 0) return fail(nullptr, SPH_EINVAL, "offsets must be non-decreasing");
+    x[s] = pos ? pos + 3 * part_off[s] : nullptr;
+    v[s] = vel ? vel + 3 * part_off[s] : nullptr;
+    y[s] = agent_pos ? agent_pos + 3 * agent_off[s] : nullptr;
+    u[s] = agent_vel ? agent_vel + 3 * agent_off[s] : nullptr;
+  }
+  return sph_ctx_build(ps, n, na, x, v, y, u, hip_stream, out);
+}
+
+sph_status sph_step(sph_ctx* ctx, int32_t n_steps) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return SPH_OK;
+  sph_status s;
+  if (ctx->graph_exec && ctx->graph_steps == n_steps) {
+    hipError_t e = hipGraphLaunch(ctx->graph_exec, ctx->stream);
+    if (e != hipSuccess) return fail(ctx, SPH_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    s = SPH_OK;
+  } else {
+    s = sph_enqueue_steps(ctx, n_steps, ctx->stream);
+  }
+  if (s != SPH_OK) return s;
+  ctx->steps += n_steps;
+  if (ctx->check_finite) return check_finite(ctx);
+  return SPH_OK;
+}
+
+sph_status sph_capture(sph_ctx* ctx, int32_t n_steps) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
+  if (ctx->graph_exec) {
+    HIPCHK(hipGraphExecDestroy(ctx->graph_exec));
+    ctx->graph_exec = nullptr;
+  }
+  if (ctx->graph) {
+    HIPCHK(hipGraphDestroy(ctx->graph));
+    ctx->graph = nullptr;
+  }
+  ctx->graph_steps = 0;
+  if (n_steps == 0) return SPH_OK;
+  hipStream_t cs = ctx->capture_stream;
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  sph_status s = sph_enqueue_steps(ctx, n_steps, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &g);
+  if (s != SPH_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(ctx, SPH_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  ctx->graph = g;
+  HIPCHK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+  ctx->graph_steps = n_steps;
+  return SPH_OK;
+}
+
+sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases) {
+  if (!ctx || !phase_ms) return fail(ctx, SPH_EINVAL, "NULL argument");
+  if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
+  return sph_profile_impl(ctx, n_steps, phase_ms, n_phases);
+}
+
+const char* sph_phase_name(int32_t phase) {
+  static const char* names[kStepPhases] = {"key_count", "scan_reduce", "scan_sets", "scan_apply", "scatter",
+                                           "fixup_gather", "density", "agents", "force_integrate"};
+  return (phase >= 0 && phase < kStepPhases) ? names[phase] : nullptr;
+}
+
+sph_status sph_read(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_bytes) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  return sph_read_impl(ctx, field, dst, dst_bytes);
+}
+
+int64_t sph_field_bytes(const sph_ctx* ctx, int32_t field) {
+  if (!ctx) return SPH_EINVAL;
+  int64_t b = field_bytes(ctx, field);
+  return b < 0 ? (int64_t)SPH_EINVAL : b;
+}
+
+sph_status sph_info_get(const sph_ctx* ctx, sph_info* out) {
+  if (!ctx || !out) return fail(nullptr, SPH_EINVAL, "NULL argument");
+  const DScene& d = ctx->hs[0];
+  out->n = ctx->N;
+  out->n_agents = ctx->A;
+  for (int k = 0; k < 3; ++k) {
+    out->dims[k] = d.g.dim[k];
+    out->agent_dims[k] = d.ga.dim[k];
+  }
+  out->cells = ctx->C;
+  out->agent_cells = ctx->AC;
+  out->cell = (float)(1.0 / (double)d.g.inv);
+  out->agent_cell = (float)(1.0 / (double)d.ga.inv);
+  out->steps = ctx->steps;
+  out->device_bytes = (int64_t)ctx->bytes;
+  return SPH_OK;
+}
+
+void sph_destroy(sph_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->stream || ctx->arena) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  if (ctx->staging) (void)hipFree(ctx->staging);
+  if (ctx->arena) (void)hipFree(ctx->arena);
+  delete ctx;
+}
+
+const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

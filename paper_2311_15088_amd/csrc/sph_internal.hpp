@@ -1,0 +1,74 @@
+// sph_internal.hpp -- host-side launch plans shared by the translation units
+// of libsph.so (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph_device.hpp"
+
+namespace sph {
+
+// Device tables describing one batched counting sort over several sets.
+struct SortPlan {
+  const SortSet* sets;         // [nsets]
+  int nsets;
+  const uint32_t* prefix;      // [nsets + 1] element prefix
+  uint32_t total;              // sum of set sizes
+  const uint32_t* chunk_prefix;// [nsets + 1] scan-chunk prefix
+  uint32_t nchunks;
+  uint32_t* bsum;              // [nchunks]
+  uint32_t* counters;          // [kWorkCounters] work counters of the tiled passes, cleared by the scan
+};
+
+constexpr int kWorkCounters = 3;
+constexpr int kCounterDensity = 0, kCounterForce = 1, kCounterList = 2;
+constexpr int kTXMax = 32;  // most cells per fluid tile along x
+
+// Device arrays of the physics kernels (all scenes concatenated).
+struct PhysPlan {
+  const DScene* scenes;
+  int nscenes;
+  const uint32_t* fprefix;     // [nscenes + 1] fluid element prefix (unpadded)
+  uint32_t nf;
+  const uint32_t* aprefix;     // [nscenes + 1] agent element prefix
+  uint32_t na;
+  // fluid, cell order
+  const float *sx, *sy, *sz, *svx, *svy, *svz;
+  const uint32_t* off;
+  float* rho;
+  uint32_t* nbr;
+  unsigned long long* nmask;   // [9][nf] neighbours among each halo row's candidates (density -> force)
+  unsigned long long* pairs;   // running sum of neighbour counts
+  // tiles of kTX cells along x (all scenes concatenated)
+  const uint32_t* tprefix;     // [nscenes + 1] tile prefix
+  uint32_t ntiles;
+  int tx;                      // cells per tile along x (<= kTXMax)
+  int variant;                 // kernel variant (block size, particles per thread, LDS capacity)
+  uint32_t* tile_list;         // [ntiles] non-empty tiles of this step
+  uint32_t* counters;          // [kWorkCounters]
+  // fluid, next-step storage (written by the force kernel)
+  float *px, *py, *pz, *vx, *vy, *vz;
+  // agents: state in id order (updated in place), sorted copies, offsets
+  float *agx, *agy, *agz, *aux, *auy, *auz;
+  const float *asx, *asy, *asz, *asvx, *asvy, *asvz;
+  const uint32_t* asid;
+  const uint32_t* aoff;
+  // diagnostics (nullptr = off)
+  float *d_aint, *d_acoup, *d_steer, *d_force;  // [n][3] / [a][3]
+  uint32_t *d_touch, *d_acnt;                   // [n] / [a][4]
+};
+
+constexpr int kSortPhases = 6;  // key+count, scan reduce, scan sets, scan apply, scatter, fix-up
+void launch_sort_phase(const SortPlan& P, int phase, hipStream_t st);
+void launch_sort(const SortPlan& P, hipStream_t st);
+uint32_t scan_chunks(uint32_t ncells);
+
+constexpr int kStepPhases = kSortPhases + 3;  // + density, agents, force + integration
+uint32_t fluid_tiles(const DGrid& g, int tx);
+int fluid_variants();
+const char* fluid_variant_name(int v);
+void launch_density(const PhysPlan& P, hipStream_t st);
+void launch_agents(const PhysPlan& P, hipStream_t st);
+void launch_force(const PhysPlan& P, hipStream_t st);
+
+}  // namespace sph
