@@ -95,6 +95,99 @@ def cpu_baseline(sc, budget_s: float):
     }
 
 
+def batched_leg(sph, scenes, torch, args):
+    """512 independent dam breaks of uneven size: one batched context vs a loop of plain steps."""
+    scs = scenes.batched(args.scenes)
+    n_tot = sum(s.n for s in scs)
+    log(f"[bench] batched: {len(scs)} scenes, {n_tot} particles, {sum(s.n_agents for s in scs)} agents")
+    stream = torch.cuda.current_stream().cuda_stream
+    bat = sph.create_batch(scs, stream=stream)
+    tuned = bat.autotune(2)
+    log(f"[bench] batched autotune: {tuned}")
+    K = args.batched_steps
+    bat.step(2)
+    bat.capture(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat.step(K)  # one graph of K steps
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    bat.close()
+    # a loop of plain steps, one scene after another (K_plain steps each)
+    Kp = max(1, K // 10)
+    tp = 0.0
+    for sc in scs:
+        sim = sph.create(sc, stream=stream)
+        sim.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(Kp)
+        torch.cuda.synchronize()
+        tp += time.perf_counter() - t0
+        sim.close()
+    return {
+        "scenes": len(scs), "particles": n_tot, "steps": K,
+        "scene_steps_per_s": len(scs) * K / tb, "particle_steps_per_s": n_tot * K / tb,
+        "plain_loop_scene_steps_per_s": len(scs) * Kp / tp, "plain_loop_steps_per_scene": Kp,
+        "speedup_vs_plain_loop": (len(scs) * K / tb) / (len(scs) * Kp / tp),
+        "autotuned": tuned,
+    }
+
+
+def closure_leg(sph, scenes, torch, args):
+    """Learned coupling closure on the 4,194,304-particle / 65,536-agent workload."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    # training pairs from config-4-style runs with other seeds
+    want = args.pairs
+    X = torch.empty((want, 256), dtype=torch.int16, device=dev)
+    F = torch.empty((want, 3), dtype=torch.float32, device=dev)
+    got, seed = 0, 1
+    t0 = time.perf_counter()
+    while got < want:
+        sc = scenes.dam_break("c4", 256, 64, 256, 0.02, (0, 0, 0), (3, 1, 3), 65536, 2e-4, 100,
+                              scenes.SEED0 + 0x400 + 0x10 * seed, agents="inside")
+        sim = sph.create(sc, stream=stream, flags=sph.FLAG_FEATURES | sph.FLAG_DIAGNOSTICS)
+        for _ in range(16):
+            if got >= want:
+                break
+            sim.step(5)
+            take = min(sc.n_agents, want - got)
+            xs = torch.empty((sc.n_agents, 256), dtype=torch.int16, device=dev)
+            fs = torch.empty((sc.n_agents, 3), dtype=torch.float32, device=dev)
+            sim.read_into(sph.AGENT_FEATURES, xs)
+            sim.read_into(sph.AGENT_FORCE, fs)
+            X[got:got + take] = xs[:take]
+            F[got:got + take] = fs[:take]
+            got += take
+        sim.close()
+        seed += 1
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    log(f"[bench] closure: collected {got} pairs in {t_collect:.1f} s")
+    cl = sph.Closure(scenes.mlp_flat(scenes.mlp_init()), stream=stream)
+    rep = cl.train(X, F, epochs=args.epochs, batch=4096, lr=1e-3, val_fraction=0.1, seed=7)
+    log(f"[bench] closure: trained {rep}")
+    del X, F
+    # evaluation run: the workload itself, exact gather vs closure
+    sc = scenes.config4()
+    K = args.closure_steps
+    res = {"pairs": got, "collect_s": t_collect, "train": rep, "steps": K}
+    for name, attach in (("exact", False), ("closure", True)):
+        sim = sph.create(sc, stream=stream)
+        if attach:
+            sim.attach_closure(cl, check_every=50, max_rel_rms=0.02)
+        ph = sim.step_profiled(K)
+        res[name] = {"agents_us_per_step": 1e3 * ph["agents"] / K, "ms_per_step": sum(ph.values()) / K}
+        if attach:
+            res[name]["stats"] = sim.closure_stats()
+            sim.attach_closure(None)
+        sim.close()
+    res["coupling_speedup"] = res["exact"]["agents_us_per_step"] / res["closure"]["agents_us_per_step"]
+    cl.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +197,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--batched", action="store_true", help="add the batched-scenes comparison")
+    ap.add_argument("--scenes", type=int, default=512)
+    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--closure", action="store_true", help="add the learned-closure comparison")
+    ap.add_argument("--pairs", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--closure-steps", type=int, default=1000)
+    ap.add_argument("--headline-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the step is single-device).",
@@ -200,6 +301,10 @@ def main():
         "kernel_us_per_step": {k: 1e3 * vms / K for k, vms in phase_ms.items()},
         "graph_ms_per_step": graph_ms,
     }
+    if args.batched:
+        result["batched"] = batched_leg(sph, scenes, torch, args)
+    if args.closure:
+        result["closure"] = closure_leg(sph, scenes, torch, args)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)

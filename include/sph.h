@@ -55,6 +55,8 @@ typedef enum {
 /* Flags (sph_params.flags). */
 #define SPH_FLAG_DIAGNOSTICS 1u  /* keep per-particle / per-agent diagnostics of the last step */
 #define SPH_FLAG_CHECK_FINITE 2u /* sph_step synchronises and rejects non-finite state */
+#define SPH_FLAG_FUSED 4u        /* one persistent launch per step (grid-wide barriers between phases) */
+#define SPH_FLAG_FEATURES 8u     /* compute the closure's agent features every step (SPH_AGENT_FEATURES) */
 
 typedef struct sph_params {
   /* smoothing length h (> 0), rest density rho0, gas constant k, viscosity mu,
@@ -93,7 +95,9 @@ typedef enum {
   SPH_AGENT_KEY = 15,   /* agent cell key, id order, uint32 [a] */
   SPH_AGENT_SORTED_IDS = 16,
   SPH_AGENT_CELL_OFFSETS = 17,
-  SPH_PAIR_COUNT = 18   /* uint64 [1]: sum of SPH_NBR_COUNT over all steps since create */
+  SPH_PAIR_COUNT = 18,  /* uint64 [1]: sum of SPH_NBR_COUNT over all steps since create */
+  SPH_AGENT_FEATURES = 19,   /* bfloat16 bits, uint16 [a][256]: closure features of the last step */
+  SPH_AGENT_FORCE_MODEL = 20 /* float32 [a][3]: closure (surrogate) force of the last step */
 } sph_field;
 
 typedef struct sph_info {
@@ -141,6 +145,96 @@ sph_status sph_info_get(const sph_ctx* ctx, sph_info* out);
 /* Capture n_steps steps into a HIP graph; later sph_step(ctx, n_steps) calls
    replay it.  n_steps = 0 drops the graph. */
 sph_status sph_capture(sph_ctx* ctx, int32_t n_steps);
+
+/* Execution form of a step, chosen by sph_autotune or set directly.
+   fused = 0: one launch per phase (variant = block size / LDS window of the
+   fluid passes); fused = 1: one persistent launch per step (variant = LDS
+   windows).  tile_x = grid cells per fluid tile along x (1..32).  Every form
+   gives bit-identical results; only the speed differs. */
+typedef struct sph_tuning {
+  int32_t fused, variant, tile_x;
+  float ms_per_step; /* measured by sph_autotune (0 when set by hand) */
+} sph_tuning;
+
+/* Time steps_per_trial steps of every execution form on the context's own
+   state (the state is restored after each trial, so the simulation does not
+   advance), keep the fastest and store it in *best (may be NULL).  When the
+   environment variable SPH_AUTOTUNE_CACHE names a file, a result for the
+   same device and problem shape is reused from it and new results appended.
+   Drops a captured graph.  Synchronises the stream. */
+sph_status sph_autotune(sph_ctx* ctx, int32_t steps_per_trial, sph_tuning* best);
+sph_status sph_tuning_set(sph_ctx* ctx, const sph_tuning* t); /* drops a captured graph */
+sph_status sph_tuning_get(const sph_ctx* ctx, sph_tuning* out);
+/* Number of kernel variants of a form, and the name of one (NULL if out of range). */
+int32_t sph_variant_count(int32_t fused);
+const char* sph_variant_name(int32_t fused, int32_t variant);
+
+/* ---------------------------------------------------------------------------
+   Learned coupling closure.  A small MLP (256 -> 128 -> 128 -> 3, GELU after
+   the hidden layers; bfloat16 operands, float32 accumulation) maps an agent's
+   neighbourhood histogram to its fluid coupling force.  Features: the 4 x 4 x
+   4 block of fluid-grid cells starting at round((y - box_min) / cell) - 2 on
+   each axis, x fastest; per cell count / 8 and (mean fluid velocity - agent
+   velocity) / 0.5, zero for an empty cell; rounded to bfloat16.  Weights are
+   float32, flat order W1 [256][128], b1 [128], W2 [128][128], b2, W3 [128][3],
+   b3 (49,795 values); the network predicts F / force_scale.
+   ------------------------------------------------------------------------- */
+typedef struct sph_closure sph_closure;
+#define SPH_CLOSURE_PARAMS 49795
+#define SPH_CLOSURE_FEATURES 256
+
+typedef struct sph_train_params {
+  int32_t epochs, batch;   /* e.g. 20, 4096 */
+  float lr, beta1, beta2, eps; /* Adam: 1e-3, 0.9, 0.999, 1e-8 */
+  float val_fraction;      /* held-out fraction of the pairs, e.g. 0.1 */
+  uint32_t seed;           /* seeds the split and the shuffles */
+} sph_train_params;
+
+typedef struct sph_train_report {
+  float train_loss;        /* mean loss of the last epoch (normalised forces) */
+  float val_rel_rms;       /* sqrt(sum |F_pred - F|^2 / sum |F|^2) on the held-out pairs */
+  float force_scale;       /* root mean square training force component */
+  int32_t steps;           /* optimiser steps taken */
+  double seconds;          /* wall time of the call */
+} sph_train_report;
+
+typedef struct sph_closure_stats {
+  int32_t mode;            /* 1: the surrogate is in use between checks */
+  float last_rel_rms;      /* error of the last check */
+  int64_t checks, fallbacks, surrogate_steps, exact_steps;
+} sph_closure_stats;
+
+/* weights: SPH_CLOSURE_PARAMS float32 (host or device) or NULL (zeros). */
+sph_status sph_closure_create(const float* weights, float force_scale, void* hip_stream, sph_closure** out);
+/* Train with Adam on n (feature, exact force) pairs held in device memory:
+   features uint16 bfloat16 bits [n][256], forces float32 [n][3].  Sets the
+   force scale, keeps the weights in the closure; synchronises. */
+sph_status sph_closure_train(sph_closure* cl, const uint16_t* features, const float* forces, int64_t n,
+                             const sph_train_params* params, sph_train_report* report);
+/* forces [n][3] = MLP(features) * force_scale (device pointers; asynchronous). */
+sph_status sph_closure_predict(sph_closure* cl, const uint16_t* features, int64_t n, float* forces);
+/* Gradient of the mean squared error between MLP(features) and forces /
+   force_scale with respect to the weights (flat order), and that loss;
+   device pointers for the inputs, host or device for grad / loss; synchronises. */
+sph_status sph_closure_gradient(sph_closure* cl, const uint16_t* features, const float* forces, int64_t n,
+                                float* grad, float* loss);
+/* One Adam step (t >= 1) with the given gradient (host or device); the moments persist in the closure. */
+sph_status sph_closure_adam_step(sph_closure* cl, const float* grad, int32_t t, float lr, float beta1, float beta2,
+                                 float eps);
+/* write = 0: copy the weights / scale out; 1: load them (either pointer may be NULL). */
+sph_status sph_closure_weights(sph_closure* cl, int32_t write, float* weights, float* force_scale);
+void sph_closure_destroy(sph_closure* cl);
+const char* sph_closure_last_error(const sph_closure* cl);
+/* Use cl for the agents' coupling force: every check_every steps (starting
+   with the next step) both the surrogate and the exact gather run and
+   rel_rms = sqrt(sum |F_pred - F|^2 / sum |F|^2) is measured on the device;
+   the steps until the next check use the surrogate only if rel_rms <=
+   max_rel_rms, the exact gather otherwise.  The fluid side always feels the
+   exact reaction.  cl = NULL detaches.  The context does not own cl; it must
+   outlive the attachment.  Drops a captured graph; steps run as per-phase
+   launches while a closure is attached. */
+sph_status sph_closure_attach(sph_ctx* ctx, sph_closure* cl, int32_t check_every, float max_rel_rms);
+sph_status sph_closure_stats_get(sph_ctx* ctx, sph_closure_stats* out);
 
 /* Profiling: run n_steps steps eagerly (never from a captured graph),
    recording a HIP event on the context's stream before the first kernel and

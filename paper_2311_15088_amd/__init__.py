@@ -21,12 +21,13 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 
 # status codes
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENONFINITE, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
-FLAG_DIAGNOSTICS, FLAG_CHECK_FINITE = 1, 2
+FLAG_DIAGNOSTICS, FLAG_CHECK_FINITE, FLAG_FUSED, FLAG_FEATURES = 1, 2, 4, 8
+CLOSURE_PARAMS, CLOSURE_FEATURES = 49795, 256
 
 # fields (sph_field)
 POS, VEL, AGENT_POS, AGENT_VEL, DENSITY, NBR_COUNT, CELL_KEY, ACC_INT, ACC_COUPLE, TOUCHED, \
     AGENT_FORCE, AGENT_STEER, AGENT_COUNTS, SORTED_IDS, CELL_OFFSETS, AGENT_KEY, AGENT_SORTED_IDS, \
-    AGENT_CELL_OFFSETS, PAIR_COUNT = range(19)
+    AGENT_CELL_OFFSETS, PAIR_COUNT, AGENT_FEATURES, AGENT_FORCE_MODEL = range(21)
 
 _FIELD_DTYPE = {
     POS: (np.float32, 3), VEL: (np.float32, 3), AGENT_POS: (np.float32, 3), AGENT_VEL: (np.float32, 3),
@@ -34,7 +35,8 @@ _FIELD_DTYPE = {
     ACC_COUPLE: (np.float32, 3), TOUCHED: (np.uint32, 1), AGENT_FORCE: (np.float32, 3),
     AGENT_STEER: (np.float32, 3), AGENT_COUNTS: (np.uint32, 4), SORTED_IDS: (np.uint32, 1),
     CELL_OFFSETS: (np.uint32, 1), AGENT_KEY: (np.uint32, 1), AGENT_SORTED_IDS: (np.uint32, 1),
-    AGENT_CELL_OFFSETS: (np.uint32, 1), PAIR_COUNT: (np.uint64, 1),
+    AGENT_CELL_OFFSETS: (np.uint32, 1), PAIR_COUNT: (np.uint64, 1), AGENT_FEATURES: (np.uint16, 256),
+    AGENT_FORCE_MODEL: (np.float32, 3),
 }
 
 
@@ -60,6 +62,33 @@ class Params(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    """Mirror of ``sph_tuning``."""
+
+    _fields_ = [("fused", ctypes.c_int32), ("variant", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_float)]
+
+    def as_dict(self):
+        return dict(fused=self.fused, variant=self.variant, tile_x=self.tile_x, ms_per_step=self.ms_per_step,
+                    name=variant_name(self.fused, self.variant))
+
+
+class TrainParams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("val_fraction", ctypes.c_float), ("seed", ctypes.c_uint32)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("train_loss", ctypes.c_float), ("val_rel_rms", ctypes.c_float), ("force_scale", ctypes.c_float),
+                ("steps", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
+class ClosureStats(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("last_rel_rms", ctypes.c_float), ("checks", ctypes.c_int64),
+                ("fallbacks", ctypes.c_int64), ("surrogate_steps", ctypes.c_int64), ("exact_steps", ctypes.c_int64)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int64), ("n_agents", ctypes.c_int64), ("dims", ctypes.c_int32 * 3),
@@ -70,7 +99,11 @@ class Info(ctypes.Structure):
 
 
 EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_bytes", "sph_info_get",
-           "sph_capture", "sph_step_profiled", "sph_phase_name", "sph_destroy", "sph_last_error")
+           "sph_capture", "sph_step_profiled", "sph_phase_name", "sph_autotune", "sph_tuning_set",
+           "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_destroy", "sph_last_error",
+           "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
+           "sph_closure_adam_step", "sph_closure_weights", "sph_closure_destroy", "sph_closure_last_error",
+           "sph_closure_attach", "sph_closure_stats_get")
 STEP_PHASES = 9
 
 _lib = None
@@ -102,12 +135,52 @@ def lib() -> ctypes.CDLL:
         L.sph_step_profiled.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i32]
         L.sph_phase_name.restype = ctypes.c_char_p
         L.sph_phase_name.argtypes = [i32]
+        L.sph_autotune.restype = ctypes.c_int
+        L.sph_autotune.argtypes = [vp, i32, ctypes.POINTER(Tuning)]
+        L.sph_tuning_set.restype = ctypes.c_int
+        L.sph_tuning_set.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.sph_tuning_get.restype = ctypes.c_int
+        L.sph_tuning_get.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.sph_variant_count.restype = i32
+        L.sph_variant_count.argtypes = [i32]
+        L.sph_variant_name.restype = ctypes.c_char_p
+        L.sph_variant_name.argtypes = [i32, i32]
+        L.sph_closure_create.restype = ctypes.c_int
+        L.sph_closure_create.argtypes = [vp, ctypes.c_float, vp, ctypes.POINTER(vp)]
+        L.sph_closure_train.restype = ctypes.c_int
+        L.sph_closure_train.argtypes = [vp, vp, vp, i64, ctypes.POINTER(TrainParams), ctypes.POINTER(TrainReport)]
+        L.sph_closure_predict.restype = ctypes.c_int
+        L.sph_closure_predict.argtypes = [vp, vp, i64, vp]
+        L.sph_closure_gradient.restype = ctypes.c_int
+        L.sph_closure_gradient.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.sph_closure_adam_step.restype = ctypes.c_int
+        L.sph_closure_adam_step.argtypes = [vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                            ctypes.c_float]
+        L.sph_closure_weights.restype = ctypes.c_int
+        L.sph_closure_weights.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_float)]
+        L.sph_closure_destroy.restype = None
+        L.sph_closure_destroy.argtypes = [vp]
+        L.sph_closure_last_error.restype = ctypes.c_char_p
+        L.sph_closure_last_error.argtypes = [vp]
+        L.sph_closure_attach.restype = ctypes.c_int
+        L.sph_closure_attach.argtypes = [vp, vp, i32, ctypes.c_float]
+        L.sph_closure_stats_get.restype = ctypes.c_int
+        L.sph_closure_stats_get.argtypes = [vp, ctypes.POINTER(ClosureStats)]
         L.sph_destroy.restype = None
         L.sph_destroy.argtypes = [vp]
         L.sph_last_error.restype = ctypes.c_char_p
         L.sph_last_error.argtypes = [vp]
         _lib = L
     return _lib
+
+
+def variant_name(fused: int, variant: int) -> Optional[str]:
+    n = lib().sph_variant_name(int(fused), int(variant))
+    return n.decode() if n else None
+
+
+def variant_count(fused: int) -> int:
+    return int(lib().sph_variant_count(int(fused)))
 
 
 def params(d: Dict, flags: int = 0) -> Params:
@@ -197,6 +270,31 @@ class Simulation:
         _check(lib().sph_step_profiled(self._ctx, int(n), buf, STEP_PHASES), self._ctx)
         return {lib().sph_phase_name(p).decode(): buf[p] for p in range(STEP_PHASES)}
 
+    def autotune(self, steps_per_trial: int = 5) -> Dict:
+        """Time every execution form on this state (restored afterwards); keep the fastest."""
+        t = Tuning()
+        _check(lib().sph_autotune(self._ctx, int(steps_per_trial), ctypes.byref(t)), self._ctx)
+        return t.as_dict()
+
+    def set_tuning(self, fused: int, variant: int, tile_x: int) -> None:
+        t = Tuning(int(fused), int(variant), int(tile_x), 0.0)
+        _check(lib().sph_tuning_set(self._ctx, ctypes.byref(t)), self._ctx)
+
+    def tuning(self) -> Dict:
+        t = Tuning()
+        _check(lib().sph_tuning_get(self._ctx, ctypes.byref(t)), self._ctx)
+        return t.as_dict()
+
+    def attach_closure(self, closure: Optional["Closure"], check_every: int = 50, max_rel_rms: float = 0.02) -> None:
+        self._closure = closure  # keeps the closure alive while attached
+        _check(lib().sph_closure_attach(self._ctx, closure._cl if closure else None, int(check_every),
+                                        float(max_rel_rms)), self._ctx)
+
+    def closure_stats(self) -> Dict:
+        st = ClosureStats()
+        _check(lib().sph_closure_stats_get(self._ctx, ctypes.byref(st)), self._ctx)
+        return {k: getattr(st, k) for k, _ in ClosureStats._fields_}
+
     def field_bytes(self, field: int) -> int:
         b = lib().sph_field_bytes(self._ctx, int(field))
         if b < 0:
@@ -252,3 +350,84 @@ def create(scene, stream: int = 0, flags: int = 0) -> Simulation:
 def create_batch(scene_list, stream: int = 0, flags: int = 0) -> Simulation:
     return Simulation.batch([s.params for s in scene_list], [s.x for s in scene_list], [s.v for s in scene_list],
                             [s.y for s in scene_list], [s.u for s in scene_list], stream=stream, flags=flags)
+
+
+def _cl_check(status: int, cl=None):
+    if status != OK:
+        msg = lib().sph_closure_last_error(cl).decode(errors="replace")
+        raise SphError(status, msg)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (must be contiguous)."""
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Closure:
+    """The learned coupling closure (weights, Adam state) on the device."""
+
+    def __init__(self, weights=None, force_scale: float = 1.0, stream: int = 0):
+        self._cl = ctypes.c_void_p()
+        keep = None
+        ptr = None
+        if weights is not None:
+            if hasattr(weights, "data_ptr"):
+                keep = weights.contiguous()
+                ptr = keep.data_ptr()
+            else:
+                keep = np.ascontiguousarray(np.asarray(weights, np.float32).ravel())
+                if keep.size != CLOSURE_PARAMS:
+                    raise ValueError(f"need {CLOSURE_PARAMS} weights")
+                ptr = keep.ctypes.data
+        _cl_check(lib().sph_closure_create(ptr, float(force_scale), ctypes.c_void_p(stream), ctypes.byref(self._cl)))
+
+    def train(self, features, forces, epochs=20, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              val_fraction=0.1, seed=0) -> Dict:
+        """features: device tensor [n, 256] of bfloat16 bits; forces: device float32 [n, 3]."""
+        tp = TrainParams(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                         float(val_fraction), int(seed))
+        rep = TrainReport()
+        _cl_check(lib().sph_closure_train(self._cl, _dptr(features), _dptr(forces), int(features.shape[0]),
+                                          ctypes.byref(tp), ctypes.byref(rep)), self._cl)
+        return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+
+    def predict(self, features, out):
+        _cl_check(lib().sph_closure_predict(self._cl, _dptr(features), int(features.shape[0]), _dptr(out)), self._cl)
+        return out
+
+    def gradient(self, features, forces):
+        g = np.zeros(CLOSURE_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        _cl_check(lib().sph_closure_gradient(self._cl, _dptr(features), _dptr(forces), int(features.shape[0]),
+                                             g.ctypes.data, ctypes.addressof(loss)), self._cl)
+        return g, loss.value
+
+    def adam_step(self, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        g = np.ascontiguousarray(np.asarray(grad, np.float32))
+        _cl_check(lib().sph_closure_adam_step(self._cl, g.ctypes.data, int(t), float(lr), float(beta1), float(beta2),
+                                              float(eps)), self._cl)
+
+    def weights(self):
+        w = np.zeros(CLOSURE_PARAMS, np.float32)
+        sc = ctypes.c_float()
+        _cl_check(lib().sph_closure_weights(self._cl, 0, w.ctypes.data, ctypes.byref(sc)), self._cl)
+        return w, sc.value
+
+    def set_weights(self, w=None, force_scale=None):
+        arr = None if w is None else np.ascontiguousarray(np.asarray(w, np.float32))
+        sc = None if force_scale is None else ctypes.c_float(float(force_scale))
+        _cl_check(lib().sph_closure_weights(self._cl, 1, None if arr is None else arr.ctypes.data,
+                                            None if sc is None else ctypes.byref(sc)), self._cl)
+
+    def close(self):
+        if self._cl:
+            lib().sph_closure_destroy(self._cl)
+            self._cl = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

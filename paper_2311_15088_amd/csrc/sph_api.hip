@@ -236,16 +236,20 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ctx->C = (uint32_t)C;
   ctx->AC = (uint32_t)AC;
   ctx->diag = (params[0].flags & SPH_FLAG_DIAGNOSTICS) != 0;
+  ctx->fused = (params[0].flags & SPH_FLAG_FUSED) != 0;
+  ctx->features = (params[0].flags & SPH_FLAG_FEATURES) != 0;
   ctx->check_finite = (params[0].flags & SPH_FLAG_CHECK_FINITE) != 0;
   ctx->stream = (hipStream_t)stream;
 
   // sort sets: fluid of every scene, then agents of every scene
   const int nsets = 2 * S;
-  std::vector<uint32_t> prefix(nsets + 1, 0), chunk_prefix(nsets + 1, 0);
+  std::vector<uint32_t> prefix(nsets + 1, 0), chunk_prefix(nsets + 1, 0), bprefix(nsets + 1, 0);
   for (int t = 0; t < nsets; ++t) {
     const DScene& d = hs[t % S];
     const bool ag = t >= S;
-    prefix[t + 1] = prefix[t] + (ag ? d.na : d.n);
+    const uint32_t ne = ag ? d.na : d.n;
+    prefix[t + 1] = prefix[t] + ne;
+    bprefix[t + 1] = bprefix[t] + (ne + kSortBD - 1) / kSortBD;
     chunk_prefix[t + 1] = chunk_prefix[t] + scan_chunks(ag ? d.ga.ncells : d.g.ncells);
   }
   ctx->nsets = nsets;
@@ -288,6 +292,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->bsum, ctx->nchunks);
   ar.add(ctx->d_sets, nsets);
   ar.add(ctx->d_prefix, nsets + 1);
+  ar.add(ctx->d_bprefix, nsets + 1);
   ar.add(ctx->d_chunk_prefix, nsets + 1);
   ar.add(ctx->d_scenes, S);
   ar.add(ctx->d_fprefix, S + 1);
@@ -297,6 +302,8 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->d_counters, kWorkCounters);
   ar.add(ctx->d_tile_list, tprefix[S]);
   ar.add(ctx->d_flag, 1);
+  ar.add(ctx->d_bar, 2);
+  ar.add(ctx->d_abort, 1);
   ctx->bytes = ar.total();
   hipError_t e = hipMalloc((void**)&ctx->arena, ctx->bytes);
   if (e != hipSuccess) {
@@ -356,6 +363,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   }
   CHK(hipMemcpyAsync(ctx->d_sets, sets.data(), sizeof(SortSet) * nsets, hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(ctx->d_prefix, prefix.data(), 4 * (nsets + 1), hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(ctx->d_bprefix, bprefix.data(), 4 * (nsets + 1), hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(ctx->d_chunk_prefix, chunk_prefix.data(), 4 * (nsets + 1), hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(ctx->d_scenes, hs.data(), sizeof(DScene) * S, hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(ctx->d_fprefix, fprefix.data(), 4 * (S + 1), hipMemcpyHostToDevice, st));
@@ -368,6 +376,8 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   CHK(hipMemsetAsync(ctx->rho, 0, 4 * std::max<uint64_t>(N, 1), st));
   CHK(hipMemsetAsync(ctx->nbr, 0, 4 * std::max<uint64_t>(N, 1), st));
   CHK(hipMemsetAsync(ctx->d_pairs, 0, 8, st));
+  CHK(hipMemsetAsync(ctx->d_bar, 0, 8, st));
+  CHK(hipMemsetAsync(ctx->d_abort, 0, 4, st));
   if (ctx->diag) {
     CHK(hipMemsetAsync(ctx->d_aint, 0, 12 * std::max<uint64_t>(N, 1), st));
     CHK(hipMemsetAsync(ctx->d_acoup, 0, 12 * std::max<uint64_t>(N, 1), st));
@@ -414,8 +424,8 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
 
   ctx->sort.sets = ctx->d_sets;
   ctx->sort.nsets = nsets;
-  ctx->sort.prefix = ctx->d_prefix;
-  ctx->sort.total = prefix[nsets];
+  ctx->sort.bprefix = ctx->d_bprefix;
+  ctx->sort.nblocks = bprefix[nsets];
   ctx->sort.chunk_prefix = ctx->d_chunk_prefix;
   ctx->sort.nchunks = ctx->nchunks;
   ctx->sort.bsum = ctx->bsum;
@@ -443,6 +453,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   P.tx = tx;
   P.variant = variant;
   if (set_tiling(ctx, tx, variant) != SPH_OK) return bail(SPH_EHIP);
+  if (ctx->features && sph_ctx_closure_buffers(ctx) != SPH_OK) return bail(SPH_ENOMEM);
   P.counters = ctx->d_counters;
   P.px = ctx->px; P.py = ctx->py; P.pz = ctx->pz;
   P.vx = ctx->vx; P.vy = ctx->vy; P.vz = ctx->vz;
@@ -480,12 +491,46 @@ sph_status set_tiling(sph_ctx* ctx, int tx, int variant) {
 
 // ------------------------------------------------------------------- step --
 
+// Per-agent feature / closure buffers (allocated once).
+sph_status sph_ctx_closure_buffers(sph_ctx* ctx) {
+  if (ctx->cl_arena) return SPH_OK;
+  const size_t A = std::max<uint32_t>(ctx->A, 1);
+  const size_t sz[] = {2 * A * kFeat, 12 * A, 4 * A, 8 * A, 4 * kClWords, 4};
+  size_t tot = 0;
+  for (size_t b : sz) tot += align_up(b, 256);
+  hipError_t e = hipMalloc((void**)&ctx->cl_arena, tot);
+  if (e != hipSuccess) return fail(ctx, SPH_ENOMEM, "closure buffers: %s", hipGetErrorString(e));
+  char* p = ctx->cl_arena;
+  void** dst[] = {(void**)&ctx->cplan.feat, (void**)&ctx->cplan.fhat, (void**)&ctx->cplan.occ, (void**)&ctx->cplan.err,
+                  (void**)&ctx->cplan.state, (void**)&ctx->cplan.relrms};
+  for (int k = 0; k < 6; ++k) {
+    *dst[k] = p;
+    p += align_up(sz[k], 256);
+  }
+  e = hipMemsetAsync(ctx->cl_arena, 0, tot, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, SPH_EHIP, "closure buffers: %s", hipGetErrorString(e));
+  return SPH_OK;
+}
+
 sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
-  for (int32_t k = 0; k < n_steps; ++k) {
-    launch_sort(ctx->sort, st);
-    launch_density(ctx->phys, st);
-    launch_agents(ctx->phys, st);
-    launch_force(ctx->phys, st);
+  // the closure and feature collection run between phases: per-phase launches
+  if (ctx->fused && !ctx->closure && !ctx->features) {
+    FusedPlan F;
+    F.sort = ctx->sort;
+    F.phys = ctx->phys;
+    F.bar = ctx->d_bar;
+    F.abort_flag = ctx->d_abort;
+    for (int32_t k = 0; k < n_steps; ++k) launch_step_fused(F, ctx->fused_variant, st);
+  } else {
+    for (int32_t k = 0; k < n_steps; ++k) {
+      launch_sort(ctx->sort, st);
+      launch_density(ctx->phys, st);
+      sph_ctx_closure_phase(ctx, st);
+      launch_agents(ctx->phys, st);
+      launch_force(ctx->phys, st);
+      sph_ctx_closure_end(ctx, st);
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, SPH_EHIP, "kernel launch: %s", hipGetErrorString(e));
@@ -496,8 +541,13 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
 static void launch_phase(sph_ctx* ctx, int p, hipStream_t st) {
   if (p < kSortPhases) launch_sort_phase(ctx->sort, p, st);
   else if (p == kSortPhases) launch_density(ctx->phys, st);
-  else if (p == kSortPhases + 1) launch_agents(ctx->phys, st);
-  else launch_force(ctx->phys, st);
+  else if (p == kSortPhases + 1) {
+    sph_ctx_closure_phase(ctx, st);
+    launch_agents(ctx->phys, st);
+  } else {
+    launch_force(ctx->phys, st);
+    sph_ctx_closure_end(ctx, st);
+  }
 }
 
 sph_status sph_profile_impl(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases) {
@@ -555,9 +605,11 @@ static sph_status check_finite(sph_ctx* ctx) {
     uint32_t n = k < 6 ? ctx->N : ctx->A;
     if (n) hipLaunchKernelGGL(k_check_finite, dim3((n + 255) / 256), dim3(256), 0, st, arrs[k], n, ctx->d_flag);
   }
-  int flag = 0;
+  int flag = 0, aborted = 0;
   HIPCHK(hipMemcpyAsync(&flag, ctx->d_flag, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&aborted, ctx->d_abort, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (aborted) return fail(ctx, SPH_EHIP, "a grid barrier of the fused step timed out");
   if (flag) return fail(ctx, SPH_ENONFINITE, "non-finite position or velocity in the state");
   return SPH_OK;
 }
@@ -634,6 +686,8 @@ int64_t field_bytes(const sph_ctx* ctx, int32_t f) {
     case SPH_AGENT_KEY: case SPH_AGENT_SORTED_IDS: return 4 * A;
     case SPH_AGENT_CELL_OFFSETS: return 4 * ((int64_t)ctx->AC + ctx->nscenes);
     case SPH_PAIR_COUNT: return 8;
+    case SPH_AGENT_FEATURES: return 2 * kFeat * A;
+    case SPH_AGENT_FORCE_MODEL: return 12 * A;
     default: return -1;
   }
 }
@@ -647,6 +701,8 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
   const bool is_diag = field == SPH_ACC_INT || field == SPH_ACC_COUPLE || field == SPH_TOUCHED ||
                        field == SPH_AGENT_FORCE || field == SPH_AGENT_STEER || field == SPH_AGENT_COUNTS;
   if (is_diag && !ctx->diag) return fail(ctx, SPH_ESTATE, "diagnostics were not enabled (SPH_FLAG_DIAGNOSTICS)");
+  if ((field == SPH_AGENT_FEATURES || field == SPH_AGENT_FORCE_MODEL) && !ctx->cl_arena)
+    return fail(ctx, SPH_ESTATE, "features are computed only with SPH_FLAG_FEATURES or an attached closure");
   if (need == 0) return SPH_OK;
   hipStream_t st = ctx->stream;
   if (!ctx->staging || ctx->staging_bytes < (size_t)need) {
@@ -717,6 +773,12 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
     case SPH_PAIR_COUNT:
       HIPCHK(hipMemcpyAsync(out, ctx->d_pairs, 8, hipMemcpyDeviceToDevice, st));
       break;
+    case SPH_AGENT_FEATURES:
+      HIPCHK(hipMemcpyAsync(out, ctx->cplan.feat, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_AGENT_FORCE_MODEL:
+      HIPCHK(hipMemcpyAsync(out, ctx->cplan.fhat, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(dst, out, (size_t)need, hipMemcpyDefault, st));
@@ -724,6 +786,193 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
   bool device_dst = hipPointerGetAttributes(&attr, dst) == hipSuccess && attr.type == hipMemoryTypeDevice;
   (void)hipGetLastError();
   if (!device_dst) HIPCHK(hipStreamSynchronize(st));
+  return SPH_OK;
+}
+
+// --------------------------------------------------------------- autotune --
+
+static sph_status drop_graph(sph_ctx* ctx) {
+  if (ctx->graph_exec) HIPCHK(hipGraphExecDestroy(ctx->graph_exec));
+  if (ctx->graph) HIPCHK(hipGraphDestroy(ctx->graph));
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->graph_steps = 0;
+  return SPH_OK;
+}
+
+static sph_status apply_tuning(sph_ctx* ctx, const sph_tuning& t) {
+  const int nv = t.fused ? fused_variant_count() : fluid_variants();
+  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || t.tile_x < 1 || t.tile_x > kTXMax)
+    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile_x %d)", t.fused, t.variant, t.tile_x);
+  sph_status st = drop_graph(ctx);
+  if (st != SPH_OK) return st;
+  st = set_tiling(ctx, t.tile_x, t.fused ? ctx->phys.variant : t.variant);
+  if (st != SPH_OK) return st;
+  ctx->fused = t.fused != 0;
+  if (t.fused) ctx->fused_variant = t.variant;
+  ctx->tuned_ms = t.ms_per_step;
+  return SPH_OK;
+}
+
+static void current_tuning(const sph_ctx* ctx, sph_tuning* t) {
+  t->fused = ctx->fused ? 1 : 0;
+  t->variant = ctx->fused ? ctx->fused_variant : ctx->phys.variant;
+  t->tile_x = ctx->phys.tx;
+  t->ms_per_step = ctx->tuned_ms;
+}
+
+// Device copy of everything a step reads from the previous one, and of every
+// field sph_read exposes, so that a tuning run leaves no trace.
+struct Snapshot {
+  char* buf = nullptr;
+  std::vector<std::pair<void*, size_t>> parts;
+};
+
+static sph_status snapshot(sph_ctx* ctx, Snapshot& sn, bool save) {
+  const size_t N = ctx->N, A = ctx->A;
+  if (sn.parts.empty()) {
+    void* f[] = {ctx->px, ctx->py, ctx->pz, ctx->vx, ctx->vy, ctx->vz, ctx->sid};
+    for (void* p : f) sn.parts.push_back({p, 4 * N});
+    void* a[] = {ctx->agx, ctx->agy, ctx->agz, ctx->aux, ctx->auy, ctx->auz};
+    for (void* p : a) sn.parts.push_back({p, 4 * A});
+    sn.parts.push_back({ctx->d_pairs, 8});
+    sn.parts.push_back({ctx->rho, 4 * N});
+    sn.parts.push_back({ctx->nbr, 4 * N});
+    sn.parts.push_back({ctx->off, 4 * ((size_t)ctx->C + ctx->nscenes)});
+    sn.parts.push_back({ctx->akey, 4 * A});
+    sn.parts.push_back({ctx->asid, 4 * A});
+    sn.parts.push_back({ctx->aoff, 4 * ((size_t)ctx->AC + ctx->nscenes)});
+    if (ctx->diag) {
+      sn.parts.push_back({ctx->d_aint, 12 * N});
+      sn.parts.push_back({ctx->d_acoup, 12 * N});
+      sn.parts.push_back({ctx->d_touch, 4 * N});
+      sn.parts.push_back({ctx->d_force, 12 * A});
+      sn.parts.push_back({ctx->d_steer, 12 * A});
+      sn.parts.push_back({ctx->d_acnt, 16 * A});
+    }
+    if (ctx->cl_arena) {
+      sn.parts.push_back({ctx->cplan.feat, 2 * (size_t)kFeat * A});
+      sn.parts.push_back({ctx->cplan.fhat, 12 * A});
+      sn.parts.push_back({ctx->cplan.state, 4 * (size_t)kClWords});
+      sn.parts.push_back({ctx->cplan.relrms, 4});
+    }
+  }
+  if (!sn.buf) {
+    size_t tot = 0;
+    for (auto& p : sn.parts) tot += p.second;
+    HIPCHK(hipMalloc((void**)&sn.buf, std::max<size_t>(tot, 8)));
+  }
+  size_t o = 0;
+  for (auto& p : sn.parts) {
+    if (p.second) {
+      void* dst = save ? (void*)(sn.buf + o) : p.first;
+      const void* src = save ? p.first : (const void*)(sn.buf + o);
+      HIPCHK(hipMemcpyAsync(dst, src, p.second, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    o += p.second;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return SPH_OK;
+}
+
+static std::string tuning_key(const sph_ctx* ctx) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::string name = "gpu";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) name = prop.gcnArchName;
+  for (auto& c : name)
+    if (c == ' ' || c == ':') c = '_';
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the problem shape
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(ctx->nscenes);
+  mix(ctx->N);
+  mix(ctx->A);
+  mix(ctx->C);
+  mix(ctx->AC);
+  char buf[64];
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return name + "/" + buf;
+}
+
+static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_out) {
+  if (steps <= 0) return fail(ctx, SPH_EINVAL, "steps_per_trial must be > 0");
+  const std::string key = tuning_key(ctx);
+  const char* cache = getenv("SPH_AUTOTUNE_CACHE");
+  if (cache && *cache) {
+    FILE* f = fopen(cache, "r");
+    if (f) {
+      char k[256];
+      sph_tuning t;
+      sph_tuning found{};
+      bool hit = false;
+      while (fscanf(f, "%255s %d %d %d %f", k, &t.fused, &t.variant, &t.tile_x, &t.ms_per_step) == 5)
+        if (key == k) {
+          found = t;
+          hit = true;
+        }
+      fclose(f);
+      if (hit && apply_tuning(ctx, found) == SPH_OK) {
+        if (best_out) *best_out = found;
+        return SPH_OK;
+      }
+    }
+  }
+  Snapshot sn;
+  sph_status st = snapshot(ctx, sn, true);
+  if (st != SPH_OK) return st;
+  const int64_t steps0 = ctx->steps;
+  sph_tuning best{};
+  best.ms_per_step = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<sph_tuning> cands;
+  const int txs[] = {8, 16, 32};
+  for (int fused = 0; fused <= 1; ++fused)
+    for (int v = 0; v < (fused ? fused_variant_count() : fluid_variants()); ++v)
+      for (int tx : txs) cands.push_back(sph_tuning{fused, v, tx, 0.0f});
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(ctx, SPH_EHIP, "event create");
+  for (size_t c = 0; c < cands.size() && st == SPH_OK; ++c) {
+    st = apply_tuning(ctx, cands[c]);
+    if (st != SPH_OK) break;
+    st = sph_enqueue_steps(ctx, 1, ctx->stream);  // warm-up (first launch of a kernel)
+    if (st != SPH_OK) break;
+    hipError_t he = hipEventRecord(e0, ctx->stream);
+    if (he == hipSuccess) st = sph_enqueue_steps(ctx, steps, ctx->stream);
+    if (he == hipSuccess && st == SPH_OK) he = hipEventRecord(e1, ctx->stream);
+    if (he == hipSuccess && st == SPH_OK) he = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (he == hipSuccess && st == SPH_OK) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) st = fail(ctx, SPH_EHIP, "autotune trial: %s", hipGetErrorString(he));
+    if (st != SPH_OK) break;
+    int aborted = 0;
+    if (hipMemcpy(&aborted, ctx->d_abort, 4, hipMemcpyDeviceToHost) != hipSuccess || aborted) {
+      st = fail(ctx, SPH_EHIP, "a grid barrier of the fused step timed out during autotuning");
+      break;
+    }
+    cands[c].ms_per_step = ms / (float)steps;
+    if (cands[c].ms_per_step < best.ms_per_step) best = cands[c];
+    st = snapshot(ctx, sn, false);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (sn.buf) (void)hipFree(sn.buf);
+  ctx->steps = steps0;
+  if (st != SPH_OK) return st;
+  st = apply_tuning(ctx, best);
+  if (st != SPH_OK) return st;
+  if (cache && *cache) {
+    FILE* f = fopen(cache, "a");
+    if (f) {
+      fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), best.fused, best.variant, best.tile_x, best.ms_per_step);
+      fclose(f);
+    }
+  }
+  if (best_out) *best_out = best;
   return SPH_OK;
 }
 
@@ -856,9 +1105,32 @@ void sph_destroy(sph_ctx* ctx) {
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->staging) (void)hipFree(ctx->staging);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->cl_arena) (void)hipFree(ctx->cl_arena);
   delete ctx;
 }
 
 const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+sph_status sph_autotune(sph_ctx* ctx, int32_t steps_per_trial, sph_tuning* best) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  return autotune_impl(ctx, steps_per_trial, best);
+}
+
+sph_status sph_tuning_set(sph_ctx* ctx, const sph_tuning* t) {
+  if (!ctx || !t) return fail(ctx, SPH_EINVAL, "NULL argument");
+  return apply_tuning(ctx, *t);
+}
+
+sph_status sph_tuning_get(const sph_ctx* ctx, sph_tuning* out) {
+  if (!ctx || !out) return fail(nullptr, SPH_EINVAL, "NULL argument");
+  current_tuning(ctx, out);
+  return SPH_OK;
+}
+
+int32_t sph_variant_count(int32_t fused) { return fused ? fused_variant_count() : fluid_variants(); }
+
+const char* sph_variant_name(int32_t fused, int32_t variant) {
+  return fused ? fused_variant_name(variant) : fluid_variant_name(variant);
+}
 
 }  // extern "C"

@@ -9,6 +9,9 @@
 #include "sph.h"
 #include "sph_device.hpp"
 #include "sph_internal.hpp"
+#include "sph_mlp.hpp"
+
+struct sph_closure;
 
 struct sph_ctx {
   std::string err;
@@ -42,7 +45,7 @@ struct sph_ctx {
   // tables
   uint32_t* bsum;
   sph::SortSet* d_sets;
-  uint32_t *d_prefix, *d_chunk_prefix, *d_fprefix, *d_aprefix;
+  uint32_t *d_prefix, *d_bprefix, *d_chunk_prefix, *d_fprefix, *d_aprefix;
   sph::DScene* d_scenes;
   unsigned long long* d_pairs;
   uint32_t* d_tprefix;
@@ -55,6 +58,12 @@ struct sph_ctx {
 
   sph::SortPlan sort;
   sph::PhysPlan phys;
+  // execution form: per-phase launches or one fused launch per step
+  bool fused = false;
+  int fused_variant = 0;
+  uint32_t* d_bar;   // [2] grid-barrier counter, generation
+  int* d_abort;      // fused barrier timed out (sticky)
+  float tuned_ms = 0.0f;
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -62,6 +71,12 @@ struct sph_ctx {
 
   void* staging = nullptr;  // readback staging (allocated on first read)
   size_t staging_bytes = 0;
+
+  // learned coupling closure (not owned) and per-agent feature buffers
+  sph_closure* closure = nullptr;
+  bool features = false;     // compute features every step (training-data collection)
+  sph::ClosurePlan cplan{};  // buffers allocated on first use
+  char* cl_arena = nullptr;
 };
 
 sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vector<int64_t>& n,
@@ -70,3 +85,6 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
                          const std::vector<const float*>& avel, void* stream, sph_ctx** out);
 sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st);
 sph_status set_tiling(sph_ctx* ctx, int tx, int variant);
+sph_status sph_ctx_closure_buffers(sph_ctx* ctx);
+void sph_ctx_closure_phase(sph_ctx* ctx, hipStream_t st);
+void sph_ctx_closure_end(sph_ctx* ctx, hipStream_t st);

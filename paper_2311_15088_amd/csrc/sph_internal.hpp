@@ -9,16 +9,24 @@
 namespace sph {
 
 // Device tables describing one batched counting sort over several sets.
+constexpr int kSortBD = 256;  // block size of the per-element sort kernels
+
 struct SortPlan {
   const SortSet* sets;         // [nsets]
   int nsets;
-  const uint32_t* prefix;      // [nsets + 1] element prefix
-  uint32_t total;              // sum of set sizes
+  const uint32_t* bprefix;     // [nsets + 1] prefix of kSortBD-element blocks per set
+  uint32_t nblocks;
   const uint32_t* chunk_prefix;// [nsets + 1] scan-chunk prefix
   uint32_t nchunks;
   uint32_t* bsum;              // [nchunks]
   uint32_t* counters;          // [kWorkCounters] work counters of the tiled passes, cleared by the scan
 };
+
+// closure controller state words: step counter, mode (1 = surrogate), use
+// the surrogate this step, check step, checks, failed checks, steps taken with
+// the surrogate / the exact gather, surrogate needed this step (use || check)
+constexpr int kClStep = 0, kClMode = 1, kClUse = 2, kClCheck = 3, kClChecks = 4, kClFallbacks = 5,
+              kClSurrogateSteps = 6, kClExactSteps = 7, kClNeed = 8, kClWords = 9;
 
 constexpr int kWorkCounters = 3;
 constexpr int kCounterDensity = 0, kCounterForce = 1, kCounterList = 2;
@@ -53,6 +61,11 @@ struct PhysPlan {
   const float *asx, *asy, *asz, *asvx, *asvy, *asvz;
   const uint32_t* asid;
   const uint32_t* aoff;
+  // learned closure (nullptr = none): surrogate forces, controller state,
+  // per-agent error terms at check steps
+  const float* cl_fhat;
+  const uint32_t* cl_state;
+  float* cl_err;
   // diagnostics (nullptr = off)
   float *d_aint, *d_acoup, *d_steer, *d_force;  // [n][3] / [a][3]
   uint32_t *d_touch, *d_acnt;                   // [n] / [a][4]
@@ -70,5 +83,17 @@ const char* fluid_variant_name(int v);
 void launch_density(const PhysPlan& P, hipStream_t st);
 void launch_agents(const PhysPlan& P, hipStream_t st);
 void launch_force(const PhysPlan& P, hipStream_t st);
+
+// One persistent launch per step (all phases, grid-wide barriers).
+constexpr int kFusedBD = 256;
+struct FusedPlan {
+  SortPlan sort;
+  PhysPlan phys;
+  uint32_t* bar;    // [2] arrival counter, generation
+  int* abort_flag;  // sticky: a barrier wait timed out
+};
+void launch_step_fused(const FusedPlan& F, int variant, hipStream_t st);
+int fused_variant_count();
+const char* fused_variant_name(int v);
 
 }  // namespace sph

@@ -1,628 +1,25 @@
-// sph_physics.hip -- density, forces, boid steering, coupling and integration.
-//
-// Fluid passes (density, then forces + integration) are persistent, LDS-tiled
-// kernels.  All particles are in cell order (the (key, id) order of this
-// step), so the 27 cells around any particle are nine rows of three
-// consecutive cells, and each row is one contiguous span of the sorted SoA
-// arrays.  A tile is kTX consecutive cells of one grid row; its halo is the
-// nine rows (y +- 1, z +- 1) over the cells cx0 - 1 .. cx1 + 1, i.e. nine
-// contiguous spans.  A workgroup stages the concatenated halo spans into LDS
-// (float4 per particle, coalesced loads) and every own particle then tests
-// only its own candidate cells, read from LDS:
-//   * a row whose y/z slab lies farther than h from the particle is skipped;
-//   * in the remaining rows only the cells that intersect [x - e, x + e]
-//     (e = sqrt(h^2 - d_yz^2)) are scanned.
-// Both cuts are conservative (a margin absorbs float32 rounding of the cell
-// boundaries), so the neighbour sets are exactly those of the 27-cell test.
-// Workgroups take chunks of 64 tiles from a counter and skip empty tiles with
-// one parallel check, so the empty part of the box costs almost nothing.
-//
-//   density  rho_i = m W_poly6 over the particle and its neighbours
-//            (Section "Smoothed Particle Hydrodynamics", poly6 kernel);
-//            |N_i| with the exact float32 test r^2 < h^2.
-//   force    symmetrised pressure + viscosity pair terms (Section "Pressure
-//            and Viscosity"), divided by rho_i; the reaction of the agents
-//            within r_couple (staged per tile in LDS); gravity; Euler-Cromer
-//            and reflecting walls; the new state is written to the storage
-//            arrays in this step's cell order.
-//   agents   one wavefront per agent: separation / alignment / cohesion over
-//            the agents in range and the coupling force summed over the fluid
-//            within r_couple (Section "Boid Motion and Agent Fluid
-//            Interaction"), then u += dt a, speed clamp, y += dt u, walls.
-#include "sph_device.hpp"
-#include "sph_internal.hpp"
+// sph_physics.hip -- per-phase kernels of the fluid and agent passes and their
+// launch configurations; the bodies are in sph_fluid_impl.hpp.
+#include "sph_fluid_impl.hpp"
 
 namespace sph {
 
-constexpr int kAgentCap = 256;   // agents staged per tile
-constexpr int kAgentRows = 64;   // agent-grid rows scanned per tile
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Number of tiles (rows x segments) of a scene's fluid grid.
-__host__ __device__ inline uint32_t tiles_of(const DGrid& g, int tx) {
-  return (uint32_t)((g.dim[0] + tx - 1) / tx) * (uint32_t)g.dim[1] * (uint32_t)g.dim[2];
-}
-
-struct TileGeom {
-  int s;            // scene
-  int cx0, cx1, cy, cz;
-  uint32_t p0, p1;  // own particles (scene-local sorted range)
-};
-
-__device__ __forceinline__ TileGeom tile_geom(const PhysPlan& P, uint32_t t) {
-  TileGeom G;
-  G.s = find_set(P.tprefix, P.nscenes, t);
-  const DScene& S = P.scenes[G.s];
-  const uint32_t lt = t - P.tprefix[G.s];
-  const uint32_t nseg = (uint32_t)((S.g.dim[0] + P.tx - 1) / P.tx);
-  const uint32_t seg = lt % nseg, row = lt / nseg;
-  G.cy = (int)(row % (uint32_t)S.g.dim[1]);
-  G.cz = (int)(row / (uint32_t)S.g.dim[1]);
-  G.cx0 = (int)seg * P.tx;
-  G.cx1 = min(G.cx0 + P.tx, S.g.dim[0]) - 1;
-  const uint32_t* off = P.off + S.obase;
-  G.p0 = off[hash3(S.g, G.cx0, G.cy, G.cz)];
-  G.p1 = off[hash3(S.g, G.cx1, G.cy, G.cz) + 1];
-  return G;
-}
-
-// Conservative candidate cells of a particle in halo row (dy, dz): the cells
-// cx-1..cx+1 (clipped to the grid) that can hold a point within h.  Returns
-// false when the whole row is out of reach.
-__device__ __forceinline__ bool row_cells(const DScene& S, float x, float y, float z, int cx, int cy, int cz, int dy,
-                                          int dz, float h, int& lo, int& hi) {
-  const DGrid& g = S.g;
-  const float d = g.cell;
-  const float slack = 1e-3f * d;  // >> float32 error of a cell boundary
-  float gy = 0.0f, gz = 0.0f;
-  if (dy > 0) gy = g.mn[1] + (float)(cy + 1) * d - y;
-  else if (dy < 0) gy = y - (g.mn[1] + (float)cy * d);
-  if (dz > 0) gz = g.mn[2] + (float)(cz + 1) * d - z;
-  else if (dz < 0) gz = z - (g.mn[2] + (float)cz * d);
-  gy = fmaxf(gy - slack, 0.0f);
-  gz = fmaxf(gz - slack, 0.0f);
-  const float q2 = gy * gy + gz * gz;
-  const float hh = h * h;
-  if (q2 >= hh) return false;
-  const float e = sqrtf(hh - q2) + slack;
-  lo = max(cx - 1, 0);
-  hi = min(cx + 1, g.dim[0] - 1);
-  const float left = g.mn[0] + (float)cx * d;
-  const float right = left + d;
-  if (x - e >= left) lo = max(lo, cx);
-  if (x + e < right) hi = min(hi, cx);
-  return true;
-}
-
-// List of the non-empty tiles of this step (order is immaterial: every
-// particle's sums depend only on its own candidate order).
-__global__ void __launch_bounds__(256) k_tile_list(PhysPlan P) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  bool busy = false;
-  if (t < P.ntiles) {
-    const TileGeom G = tile_geom(P, t);
-    busy = G.p1 > G.p0;
-  }
-  const uint64_t m = __ballot(busy);
-  if (!m) return;
-  uint32_t base = 0;
-  const int first = __ffsll((long long)m) - 1;
-  if (lane == first) base = atomicAdd(&P.counters[kCounterList], (uint32_t)__popcll(m));
-  base = __shfl(base, first);
-  if (busy) P.tile_list[base + __popcll(m & ((1ull << lane) - 1ull))] = t;
-}
-
-// ----------------------------------------------------------------------------
-// Fluid tile kernel: FORCE = false -> density pass, true -> force pass.
-//
-// LDS holds the tile's halo as a concatenated stream of the nine row spans,
-// in windows of CAP elements.  Element e lives at slot e + e/8: cells hold
-// about eight particles, and without the padding lanes of neighbouring cells
-// read the same banks.  Per halo element the force pass stages
-// (x, y, z, rho - rho0) and (vx, vy, vz, m / rho).
-//
-// The density pass records, per particle and row, which of the row's
-// candidates (at most 64) are neighbours: one 64-bit mask per row, stored
-// [row][particle].  The force pass recomputes the same candidate range and
-// evaluates only the marked pairs; a row with more than 64 candidates is
-// tested candidate by candidate instead.
-// ----------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t lds_slot(uint32_t e) { return e + (e >> 3); }
+__global__ void __launch_bounds__(256) k_tile_list(PhysPlan P) { tile_list_block(P, blockIdx.x); }
 
 template <bool FORCE, int BD, int CAP>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
-  static_assert(BD % kWave == 0, "block size");
-  constexpr int kSlots = CAP + CAP / 8;
-  __shared__ float4 s_pos[kSlots];
-  __shared__ float4 s_vel[FORCE ? kSlots : 1];
-  __shared__ uint32_t s_off[9][kTXMax + 4];
-  __shared__ uint32_t s_item;
-  // agents near the tile (force pass)
-  __shared__ float4 s_ay[FORCE ? kAgentCap : 1];
-  __shared__ float4 s_au[FORCE ? kAgentCap : 1];
-  __shared__ uint32_t s_arow_a[FORCE ? kAgentRows : 1], s_arow_n[FORCE ? kAgentRows : 1];
-  __shared__ uint32_t s_wcnt[BD / kWave];
-  __shared__ uint32_t s_nag;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
-  unsigned long long npairs = 0;
-  uint32_t* counter = P.counters + (FORCE ? kCounterForce : kCounterDensity);
-  const uint32_t nlist = P.counters[kCounterList];
-
-  for (;;) {
-    // take the next non-empty tile
-    if (tid == 0) s_item = atomicAdd(counter, 1u);
-    __syncthreads();
-    const uint32_t item = uniform_u32(s_item);
-    if (item >= nlist) break;
-    const uint32_t t = uniform_u32(P.tile_list[item]);
-    const TileGeom G = tile_geom(P, t);
-    const DScene& S = P.scenes[G.s];
-    const uint32_t* __restrict__ off = P.off + S.obase;
-    const uint32_t pb = S.pbase;
-    const int hx0 = max(G.cx0 - 1, 0), hx1 = min(G.cx1 + 1, S.g.dim[0] - 1);
-    const int nh = hx1 - hx0 + 1;
-
-    // cell offsets of the nine halo rows (rows outside the grid are empty)
-    for (int k = tid; k < 9 * (nh + 1); k += BD) {
-      const int r = k / (nh + 1), c = k % (nh + 1);
-      const int y = G.cy + (r % 3) - 1, z = G.cz + (r / 3) - 1;
-      uint32_t v = 0;
-      if (y >= 0 && y < S.g.dim[1] && z >= 0 && z < S.g.dim[2]) v = off[hash3(S.g, hx0, y, z) + c];
-      s_off[r][c] = v;
-    }
-
-    // agents whose coupling sphere can reach the tile (force pass), in a
-    // fixed order: agent-grid rows in order, each row in cell order
-    uint32_t nag = 0;
-    bool agents_global = false;
-    if constexpr (FORCE) {
-      if (S.na) {
-        const float d = S.g.cell, slack = 1e-3f * d;
-        const float rc = sqrtf(S.rc2) + slack;
-        const float lo[3] = {S.g.mn[0] + (float)G.cx0 * d - slack, S.g.mn[1] + (float)G.cy * d - slack,
-                             S.g.mn[2] + (float)G.cz * d - slack};
-        const float hi[3] = {S.g.mn[0] + (float)(G.cx1 + 1) * d + slack, S.g.mn[1] + (float)(G.cy + 1) * d + slack,
-                             S.g.mn[2] + (float)(G.cz + 1) * d + slack};
-        const DGrid& ga = S.ga;
-        const int gx0 = cell_coord(lo[0] - rc, ga.mn[0], ga.inv, ga.dim[0]);
-        const int gx1 = cell_coord(hi[0] + rc, ga.mn[0], ga.inv, ga.dim[0]);
-        const int gy0 = cell_coord(lo[1] - rc, ga.mn[1], ga.inv, ga.dim[1]);
-        const int gy1 = cell_coord(hi[1] + rc, ga.mn[1], ga.inv, ga.dim[1]);
-        const int gz0 = cell_coord(lo[2] - rc, ga.mn[2], ga.inv, ga.dim[2]);
-        const int gz1 = cell_coord(hi[2] + rc, ga.mn[2], ga.inv, ga.dim[2]);
-        const int nry = gy1 - gy0 + 1, nrows = nry * (gz1 - gz0 + 1);
-        if (nrows > kAgentRows) {
-          agents_global = true;
-        } else {
-          const uint32_t* __restrict__ aoff = P.aoff + S.aobase;
-          if (tid < nrows) {
-            const int y = gy0 + tid % nry, z = gz0 + tid / nry;
-            const uint32_t a0 = aoff[hash3(ga, gx0, y, z)], a1 = aoff[hash3(ga, gx1, y, z) + 1];
-            s_arow_a[tid] = a0;
-            s_arow_n[tid] = a1 - a0;
-          }
-          if (tid == 0) s_nag = 0;
-          __syncthreads();
-          uint32_t total = 0;
-          for (int r = 0; r < nrows; ++r) total += s_arow_n[r];
-          total = uniform_u32(total);
-          for (uint32_t base = 0; base < total; base += BD) {
-            const uint32_t e = base + tid;
-            bool keep = false;
-            float4 ay = make_float4(0, 0, 0, 0), au = ay;
-            if (e < total) {
-              uint32_t r = 0, acc = 0;
-              while (acc + s_arow_n[r] <= e) acc += s_arow_n[r++];
-              const uint32_t b = S.abase + s_arow_a[r] + (e - acc);
-              ay = make_float4(P.asx[b], P.asy[b], P.asz[b], 0.0f);
-              au = make_float4(P.asvx[b], P.asvy[b], P.asvz[b], 0.0f);
-              const float ex = fmaxf(fmaxf(lo[0] - ay.x, ay.x - hi[0]), 0.0f);
-              const float ey = fmaxf(fmaxf(lo[1] - ay.y, ay.y - hi[1]), 0.0f);
-              const float ez = fmaxf(fmaxf(lo[2] - ay.z, ay.z - hi[2]), 0.0f);
-              keep = ex * ex + ey * ey + ez * ez < rc * rc;
-            }
-            const uint64_t m = __ballot(keep);
-            if (lane == 0) s_wcnt[wave] = (uint32_t)__popcll(m);
-            __syncthreads();
-            uint32_t before = s_nag;
-            for (int w = 0; w < wave; ++w) before += s_wcnt[w];
-            const uint32_t pos = before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (keep && pos < kAgentCap) {
-              s_ay[pos] = ay;
-              s_au[pos] = au;
-            }
-            __syncthreads();
-            if (tid == 0) {
-              uint32_t add = 0;
-              for (int w = 0; w < BD / kWave; ++w) add += s_wcnt[w];
-              s_nag += add;
-            }
-            __syncthreads();
-          }
-          nag = uniform_u32(s_nag);
-          if (nag > kAgentCap) agents_global = true;
-        }
-      }
-    }
-    __syncthreads();
-
-    // row spans of the halo, concatenated (uniform across the block)
-    uint32_t rbase[10], ra[9];
-    rbase[0] = 0;
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      ra[r] = uniform_u32(s_off[r][0]);
-      rbase[r + 1] = rbase[r] + (uniform_u32(s_off[r][nh]) - ra[r]);
-    }
-    const uint32_t L = rbase[9];
-    const float h2 = S.h2;
-    const float hcut = sqrtf(S.h2) * (1.0f + 1e-5f);
-
-    for (uint32_t base = G.p0; base < G.p1; base += BD) {
-      const uint32_t li = base + tid;
-      const bool act = li < G.p1;
-      const uint32_t i = pb + (act ? li : G.p0);
-      const float xi = P.sx[i], yi = P.sy[i], zi = P.sz[i];
-      float vxi = 0.0f, vyi = 0.0f, vzi = 0.0f, di = 0.0f;
-      uint64_t mrow[9];
-      if constexpr (FORCE) {
-        vxi = P.svx[i];
-        vyi = P.svy[i];
-        vzi = P.svz[i];
-        di = P.rho[i] - S.rho0;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) mrow[r] = act ? P.nmask[(size_t)r * P.nf + i] : 0ull;
-      }
-      const int cxi = cell_coord(xi, S.g.mn[0], S.g.inv, S.g.dim[0]);
-      float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-      uint32_t cnt = 0;
-      uint64_t carry = 0;  // density: mask of a row continued from the previous window
-
-      for (uint32_t c0 = 0; c0 < L; c0 += CAP) {
-        const uint32_t len = min((uint32_t)CAP, L - c0);
-        __syncthreads();
-        for (uint32_t e = tid; e < len; e += BD) {
-          const uint32_t se = c0 + e;
-          // row holding stream element se: the last row whose start is <= se
-          uint32_t rb = rbase[0], rstart = ra[0];
-#pragma unroll
-          for (int r = 1; r < 9; ++r) {
-            if (se >= rbase[r]) {
-              rb = rbase[r];
-              rstart = ra[r];
-            }
-          }
-          const uint32_t j = pb + rstart + (se - rb);
-          if constexpr (FORCE) {
-            const float rhoj = P.rho[j];
-            s_pos[lds_slot(e)] = make_float4(P.sx[j], P.sy[j], P.sz[j], rhoj - S.rho0);
-            s_vel[lds_slot(e)] = make_float4(P.svx[j], P.svy[j], P.svz[j], S.m * __builtin_amdgcn_rcpf(rhoj));
-          } else {
-            s_pos[lds_slot(e)] = make_float4(P.sx[j], P.sy[j], P.sz[j], 0.0f);
-          }
-        }
-        __syncthreads();
-        if (!act) continue;
-        const uint32_t c1 = c0 + len;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) {
-          const int dy = (r % 3) - 1, dz = (r / 3) - 1;
-          const int y = G.cy + dy, z = G.cz + dz;
-          int lo, hi;
-          if (y < 0 || y >= S.g.dim[1] || z < 0 || z >= S.g.dim[2]) continue;
-          if (!row_cells(S, xi, yi, zi, cxi, G.cy, G.cz, dy, dz, hcut, lo, hi)) continue;
-          const uint32_t rs = rbase[r] + (s_off[r][lo - hx0] - ra[r]);
-          const uint32_t re = rbase[r] + (s_off[r][hi - hx0 + 1] - ra[r]);
-          const uint32_t a = max(rs, c0), b = min(re, c1);
-          if (a >= b) continue;
-          if constexpr (!FORCE) {
-            uint64_t mk = (a > rs) ? carry : 0ull;
-            uint64_t bit = 1ull << ((a - rs) & 63u);
-            for (uint32_t jj = a; jj < b; ++jj) {
-              const float4 qp = s_pos[lds_slot(jj - c0)];
-              const float r2 = dist2_exact(qp.x - xi, qp.y - yi, qp.z - zi);
-              // max(h^2 - r^2, 0)^3 adds exactly 0 for a non-neighbour
-              const float t3 = fmaxf(h2 - r2, 0.0f);
-              acc0 += t3 * t3 * t3;
-              const bool nb = r2 < h2;
-              cnt += nb ? 1u : 0u;
-              mk |= nb ? bit : 0ull;
-              bit <<= 1;
-            }
-            if (re <= c1) P.nmask[(size_t)r * P.nf + i] = (re - rs > 64u) ? ~0ull : mk;
-            else carry = mk;
-          } else {
-            auto pair = [&](uint32_t jj) {
-              const float4 qp = s_pos[lds_slot(jj - c0)];
-              const float dx = qp.x - xi, dy = qp.y - yi, dz = qp.z - zi;
-              const float r2 = dist2_exact(dx, dy, dz);
-              if (r2 < h2 && r2 > 0.0f) {
-                // (m/rho_j) w [Cp k h (d_i + d_j) w / r * r_ij - Cv mu v_ij],  r_ij = -(dx, dy, dz)
-                const float4 qv = s_vel[lds_slot(jj - c0)];
-                const float ir = rsqrtf(r2);
-                const float w = 1.0f - r2 * ir * S.inv_h;
-                const float sc = qv.w * w;
-                const float fp = S.cpk_h * (di + qp.w) * w * ir;
-                acc0 += sc * (-fp * dx - S.cvmu * (vxi - qv.x));
-                acc1 += sc * (-fp * dy - S.cvmu * (vyi - qv.y));
-                acc2 += sc * (-fp * dz - S.cvmu * (vzi - qv.z));
-              }
-            };
-            if (re - rs <= 64u) {
-              uint64_t mk = mrow[r];
-              const uint32_t lo_b = a - rs, hi_b = b - rs;
-              if (hi_b < 64) mk &= (1ull << hi_b) - 1ull;
-              mk &= ~((1ull << lo_b) - 1ull);
-              while (mk) {
-                const uint32_t bit = (uint32_t)__ffsll((long long)mk) - 1u;
-                mk &= mk - 1ull;
-                pair(rs + bit);
-              }
-            } else {
-              for (uint32_t jj = a; jj < b; ++jj) pair(jj);
-            }
-          }
-        }
-      }
-      if (!act) continue;
-
-      if constexpr (!FORCE) {
-        // the particle itself is in its own row (r^2 = 0): it adds W(0) but is not its own neighbour
-        P.rho[i] = S.c6m * acc0;
-        P.nbr[i] = cnt - 1;
-        npairs += cnt - 1;
-      } else {
-        const float irho = __builtin_amdgcn_rcpf(di + S.rho0);
-        const float ax = acc0 * irho, ay = acc1 * irho, az = acc2 * irho;
-        // reaction of the agents within r_couple: -G_ai / m
-        float cx = 0.0f, cy = 0.0f, cz = 0.0f;
-        uint32_t touched = 0;
-        const float mi = S.m * irho;
-        auto agent = [&](float4 ya, float4 ua) {
-          const float dx = ya.x - xi, dy = ya.y - yi, dz = ya.z - zi;
-          const float r2 = dist2_exact(dx, dy, dz);
-          if (r2 < S.rc2) {
-            ++touched;
-            if (r2 > 0.0f) {
-              const float ir = rsqrtf(r2);
-              const float w = 1.0f - r2 * ir * S.inv_rc;
-              const float sc = S.m_over_rho0 * mi * w;
-              const float fp = S.cpk_hc * di * w * ir;
-              cx -= sc * (fp * dx - S.cvmu_c * (ua.x - vxi));
-              cy -= sc * (fp * dy - S.cvmu_c * (ua.y - vyi));
-              cz -= sc * (fp * dz - S.cvmu_c * (ua.z - vzi));
-            }
-          }
-        };
-        if (!agents_global) {
-          for (uint32_t b = 0; b < nag; ++b) agent(s_ay[b], s_au[b]);
-        } else {
-          const uint32_t* __restrict__ aoff = P.aoff + S.aobase;
-          int gx, gy, gz;
-          cell_of(S.ga, xi, yi, zi, gx, gy, gz);
-          const int g0 = max(gx - 1, 0), g1 = min(gx + 1, S.ga.dim[0] - 1);
-          for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy) {
-              const int y = gy + dy, z = gz + dz;
-              if (y < 0 || y >= S.ga.dim[1] || z < 0 || z >= S.ga.dim[2]) continue;
-              const uint32_t b0 = aoff[hash3(S.ga, g0, y, z)], b1 = aoff[hash3(S.ga, g1, y, z) + 1];
-              for (uint32_t t2 = b0; t2 < b1; ++t2) {
-                const uint32_t b = S.abase + t2;
-                agent(make_float4(P.asx[b], P.asy[b], P.asz[b], 0.0f),
-                      make_float4(P.asvx[b], P.asvy[b], P.asvz[b], 0.0f));
-              }
-            }
-        }
-        cx *= S.inv_m;
-        cy *= S.inv_m;
-        cz *= S.inv_m;
-        float vx = vxi + S.dt * (ax + cx + S.grav[0]);
-        float vy = vyi + S.dt * (ay + cy + S.grav[1]);
-        float vz = vzi + S.dt * (az + cz + S.grav[2]);
-        float px = xi + S.dt * vx;
-        float py = yi + S.dt * vy;
-        float pz = zi + S.dt * vz;
-        wall(px, vx, S.bmin[0], S.bmax[0], S.e);
-        wall(py, vy, S.bmin[1], S.bmax[1], S.e);
-        wall(pz, vz, S.bmin[2], S.bmax[2], S.e);
-        P.px[i] = px;
-        P.py[i] = py;
-        P.pz[i] = pz;
-        P.vx[i] = vx;
-        P.vy[i] = vy;
-        P.vz[i] = vz;
-        if (P.d_aint) {
-          P.d_aint[3 * i + 0] = ax;
-          P.d_aint[3 * i + 1] = ay;
-          P.d_aint[3 * i + 2] = az;
-          P.d_acoup[3 * i + 0] = cx;
-          P.d_acoup[3 * i + 1] = cy;
-          P.d_acoup[3 * i + 2] = cz;
-          P.d_touch[i] = touched;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if constexpr (!FORCE) {
-    if (P.pairs) {
-      npairs = wave_sum_u64(npairs);
-      if (lane == 0 && npairs) atomicAdd(P.pairs, npairs);
-    }
-  }
+  fluid_tiles<FORCE, BD, CAP>(P);
 }
 
-// ----------------------------------------------------------------------------
-// Agents: one wavefront per agent (id order within its scene).
-// ----------------------------------------------------------------------------
 template <int BD>
 __global__ void __launch_bounds__(BD) k_agents(PhysPlan P) {
-  const uint32_t ga_ = (blockIdx.x * BD + threadIdx.x) / kWave;  // agent handled by this wave
-  const int lane = threadIdx.x & (kWave - 1);
-  if (ga_ >= P.na) return;
-  const uint32_t gi = uniform_u32(ga_);
-  const int s = find_set(P.aprefix, P.nscenes, gi);
-  const DScene& S = P.scenes[s];
-  const uint32_t la = gi - P.aprefix[s];
-  const uint32_t a = S.abase + la;
-  const float ya[3] = {P.agx[a], P.agy[a], P.agz[a]};
-  const float ua[3] = {P.aux[a], P.auy[a], P.auz[a]};
-
-  // --- boid rules over the agents in the 27 agent cells ---
-  const uint32_t* __restrict__ aoff = P.aoff + S.aobase;
-  int cx, cy, cz;
-  cell_of(S.ga, ya[0], ya[1], ya[2], cx, cy, cz);
-  float sep[3] = {0, 0, 0}, dv[3] = {0, 0, 0}, dp[3] = {0, 0, 0};
-  uint32_t nsep = 0, nali = 0, ncoh = 0;
-  {
-    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, S.ga.dim[0] - 1);
-    for (int r = 0; r < 9; ++r) {
-      const int y = cy + (r % 3) - 1, z = cz + (r / 3) - 1;
-      if (y < 0 || y >= S.ga.dim[1] || z < 0 || z >= S.ga.dim[2]) continue;
-      const uint32_t b0 = aoff[hash3(S.ga, x0, y, z)], b1 = aoff[hash3(S.ga, x1, y, z) + 1];
-      for (uint32_t t = b0 + lane; t < b1; t += kWave) {
-        const uint32_t b = S.abase + t;
-        if (P.asid[b] == la) continue;
-        const float dx = P.asx[b] - ya[0], dy = P.asy[b] - ya[1], dz = P.asz[b] - ya[2];
-        const float r2 = dist2_exact(dx, dy, dz);
-        if (r2 < S.rsep2) {
-          ++nsep;
-          const float w = fmaxf(0.0f, 1.0f - sqrtf(r2) * S.inv_rsep);
-          sep[0] -= w * dx;
-          sep[1] -= w * dy;
-          sep[2] -= w * dz;
-        }
-        if (r2 < S.rali2) {
-          ++nali;
-          dv[0] += P.asvx[b] - ua[0];
-          dv[1] += P.asvy[b] - ua[1];
-          dv[2] += P.asvz[b] - ua[2];
-        }
-        if (r2 < S.rcoh2) {
-          ++ncoh;
-          dp[0] += dx;
-          dp[1] += dy;
-          dp[2] += dz;
-        }
-      }
-    }
-  }
-
-  // --- coupling force: fluid particles within r_couple (fluid-grid stencil) ---
-  const uint32_t* __restrict__ off = P.off + S.obase;
-  cell_of(S.g, ya[0], ya[1], ya[2], cx, cy, cz);
-  float F[3] = {0, 0, 0};
-  uint32_t ncpl = 0;
-  {
-    const int ns = S.ns_c;
-    const int x0 = max(cx - ns, 0), x1 = min(cx + ns, S.g.dim[0] - 1);
-    for (int dz = -ns; dz <= ns; ++dz) {
-      const int z = cz + dz;
-      if (z < 0 || z >= S.g.dim[2]) continue;
-      for (int dy = -ns; dy <= ns; ++dy) {
-        const int y = cy + dy;
-        if (y < 0 || y >= S.g.dim[1]) continue;
-        const uint32_t j0 = off[hash3(S.g, x0, y, z)], j1 = off[hash3(S.g, x1, y, z) + 1];
-        for (uint32_t t = j0 + lane; t < j1; t += kWave) {
-          const uint32_t j = S.pbase + t;
-          const float dx = P.sx[j] - ya[0], dy_ = P.sy[j] - ya[1], dz_ = P.sz[j] - ya[2];
-          const float r2 = dist2_exact(dx, dy_, dz_);
-          if (r2 < S.rc2) {
-            ++ncpl;
-            if (r2 > 0.0f) {
-              const float ir = rsqrtf(r2);
-              const float w = 1.0f - r2 * ir * S.inv_rc;
-              const float rhoj = P.rho[j];
-              // G_aj = (m/rho0)(m/rho_j) w [Cp k rc (0 + d_j) w / r (y_a - x_j) - Cv mu (u_a - v_j)]
-              const float sc = S.m_over_rho0 * (S.m / rhoj) * w;
-              const float fp = S.cpk_hc * (rhoj - S.rho0) * w * ir;
-              F[0] += sc * (-fp * dx - S.cvmu_c * (ua[0] - P.svx[j]));
-              F[1] += sc * (-fp * dy_ - S.cvmu_c * (ua[1] - P.svy[j]));
-              F[2] += sc * (-fp * dz_ - S.cvmu_c * (ua[2] - P.svz[j]));
-            }
-          }
-        }
-      }
-    }
-  }
-
-  // --- wave reductions (fixed order: deterministic) ---
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    sep[k] = wave_sum_f(sep[k]);
-    dv[k] = wave_sum_f(dv[k]);
-    dp[k] = wave_sum_f(dp[k]);
-    F[k] = wave_sum_f(F[k]);
-  }
-  nsep = wave_sum_u(nsep);
-  nali = wave_sum_u(nali);
-  ncoh = wave_sum_u(ncoh);
-  ncpl = wave_sum_u(ncpl);
-  if (lane != 0) return;
-
-  const float ia = nali ? 1.0f / (float)nali : 0.0f;
-  const float ic = ncoh ? 1.0f / (float)ncoh : 0.0f;
-  float steer[3], un[3], yn[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    steer[k] = S.wsep * sep[k] + S.wali * dv[k] * ia + S.wcoh * dp[k] * ic;
-    un[k] = ua[k] + S.dt * (steer[k] + S.cf * F[k] * S.inv_m);
-  }
-  const float sp = sqrtf(un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-  float scale = 1.0f;
-  if (sp > S.vmax) scale = S.vmax / sp;
-  else if (sp > 0.0f && sp < S.vmin) scale = S.vmin / sp;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    un[k] *= scale;
-    yn[k] = ya[k] + S.dt * un[k];
-    wall(yn[k], un[k], S.bmin[k], S.bmax[k], S.e);
-  }
-  P.agx[a] = yn[0];
-  P.agy[a] = yn[1];
-  P.agz[a] = yn[2];
-  P.aux[a] = un[0];
-  P.auy[a] = un[1];
-  P.auz[a] = un[2];
-  if (P.d_steer) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      P.d_steer[3 * a + k] = steer[k];
-      P.d_force[3 * a + k] = F[k];
-    }
-    P.d_acnt[4 * a + 0] = nsep;
-    P.d_acnt[4 * a + 1] = nali;
-    P.d_acnt[4 * a + 2] = ncoh;
-    P.d_acnt[4 * a + 3] = ncpl;
-  }
+  agents_block<BD>(P, blockIdx.x);
 }
 
 // ----------------------------------------------------------------------------
-// Launch configurations of the fluid passes: (block size, LDS halo window of
-// the density pass, of the force pass).  They are
+// Launch configurations of the fluid passes: (block size, LDS window of the
+// density pass, of the force pass; a halo row longer than the window is
+// staged in pieces).  They are
 // instantiations of the one kernel above; every one produces bit-identical
 // results (the candidate order of each particle does not depend on them).
 struct FluidVariant {
@@ -639,11 +36,11 @@ static FluidVariant make_variant(const char* name) {
 
 static const FluidVariant* variants() {
   static const FluidVariant v[] = {
-      make_variant<256, 2048, 1024>("bd256_cap2048_1024"),
-      make_variant<128, 2048, 1024>("bd128_cap2048_1024"),
-      make_variant<256, 1024, 512>("bd256_cap1024_512"),
-      make_variant<512, 2048, 1024>("bd512_cap2048_1024"),
-      make_variant<128, 1024, 512>("bd128_cap1024_512"),
+      make_variant<256, 512, 512>("bd256_win512_512"),
+      make_variant<128, 512, 256>("bd128_win512_256"),
+      make_variant<512, 512, 512>("bd512_win512_512"),
+      make_variant<256, 1024, 1024>("bd256_win1024_1024"),
+      make_variant<256, 256, 256>("bd256_win256_256"),
   };
   return v;
 }

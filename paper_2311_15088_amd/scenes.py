@@ -257,3 +257,38 @@ def small_dam(nx=12, ny=10, nz=14, h=0.05, n_agents=24, agents="inside", seed=SE
 
 
 CONFIGS = {"c0": config0, "c0c": config0c, "c1": config1, "c2": config2, "c4": config4}
+
+
+MLP_SIZES = (256, 128, 128, 3)
+
+
+def mlp_init(seed: int = SEED0 + 0x500) -> Dict[str, np.ndarray]:
+    """Initial closure weights: Kaiming-uniform U(-b, b), b = sqrt(6 / fan_in), zero biases.
+
+    Weights are [fan_in, fan_out] float32; the flat parameter order is
+    W1, b1, W2, b2, W3, b3 (49,795 values).
+    """
+    p = {}
+    for layer in range(3):
+        fi, fo = MLP_SIZES[layer], MLP_SIZES[layer + 1]
+        b = math.sqrt(6.0 / fi)
+        u = uniform01(seed, 10 + layer, np.arange(fi * fo, dtype=np.uint64)).reshape(fi, fo)
+        p[f"W{layer + 1}"] = ((2.0 * u - 1.0) * b).astype(np.float32)
+        p[f"b{layer + 1}"] = np.zeros(fo, np.float32)
+    return p
+
+
+def mlp_flat(p: Dict[str, np.ndarray]) -> np.ndarray:
+    """Parameters in the flat order W1, b1, W2, b2, W3, b3 (float32)."""
+    return np.concatenate([np.asarray(p[k], np.float32).ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def mlp_unflat(flat: np.ndarray) -> Dict[str, np.ndarray]:
+    out, o = {}, 0
+    for layer in range(3):
+        fi, fo = MLP_SIZES[layer], MLP_SIZES[layer + 1]
+        out[f"W{layer + 1}"] = np.asarray(flat[o:o + fi * fo]).reshape(fi, fo)
+        o += fi * fo
+        out[f"b{layer + 1}"] = np.asarray(flat[o:o + fo])
+        o += fo
+    return out

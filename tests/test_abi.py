@@ -30,28 +30,42 @@ def test_library_exports_every_declared_function():
     assert set(sph.EXPORTS) <= set(names)
 
 
+MIRRORS = [("sph_params", "Params"), ("sph_info", "Info"), ("sph_tuning", "Tuning"),
+           ("sph_train_params", "TrainParams"), ("sph_train_report", "TrainReport"),
+           ("sph_closure_stats", "ClosureStats")]
+
+
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
-    fields = [f for f, _ in sph.Params._fields_]
-    body = "\n".join(f'  printf("%zu\\n", offsetof(sph_params, {f}));' for f in fields)
-    ibody = "\n".join(f'  printf("%zu\\n", offsetof(sph_info, {f}));' for f, _ in sph.Info._fields_)
+    lines = []
+    expect = []
+    for cname, pyname in MIRRORS:
+        cls = getattr(sph, pyname)
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f}));')
+            expect.append(getattr(cls, f).offset)
+    body = "\n".join(lines)
     src.write_text(f"""#include <stddef.h>
 #include <stdio.h>
 #include "sph.h"
 int main(void) {{
-  printf("%zu\\n", sizeof(sph_params));
 {body}
-  printf("%zu\\n", sizeof(sph_info));
-{ibody}
   return 0;
 }}
 """)
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    expect = [ctypes.sizeof(sph.Params)] + [getattr(sph.Params, f).offset for f in fields]
-    expect += [ctypes.sizeof(sph.Info)] + [getattr(sph.Info, f).offset for f, _ in sph.Info._fields_]
     assert vals == expect
+
+
+def test_closure_constants_match_header():
+    text = open(HEADER).read()
+    assert f"#define SPH_CLOSURE_PARAMS {sph.CLOSURE_PARAMS}" in text
+    assert f"#define SPH_CLOSURE_FEATURES {sph.CLOSURE_FEATURES}" in text
+    assert sph.CLOSURE_PARAMS == scenes.mlp_flat(scenes.mlp_init()).size
 
 
 def _try_create(p, n=4, na=2):

@@ -1,0 +1,148 @@
+"""The learned coupling closure on the GPU against the CPU oracle (oracle/mlp.py):
+features, the bfloat16 MFMA forward pass, gradients, Adam, training, and the
+device-side controller with its fallback to the exact gather."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2311_15088_amd as sph
+from oracle import mlp
+from paper_2311_15088_amd import scenes
+
+from parity import rel_scale_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def bf16_bits(x):
+    """float array -> (float64 values rounded to bfloat16, uint16 bit patterns)."""
+    r = mlp.bf16_round(x)
+    bits = (r.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return r, bits
+
+
+def to_dev_bits(bits):
+    return torch.from_numpy(np.ascontiguousarray(bits).view(np.int16)).to(DEV)
+
+
+def params_np(seed=7):
+    rng = np.random.default_rng(seed)
+    p = scenes.mlp_init(seed)
+    for k in ("b1", "b2", "b3"):
+        p[k] = (0.1 * rng.standard_normal(p[k].shape)).astype(np.float32)
+    return p
+
+
+def test_forward_matches_oracle():
+    p = params_np()
+    rng = np.random.default_rng(1)
+    X, bits = bf16_bits(rng.standard_normal((1000, 256)))
+    cl = sph.Closure(scenes.mlp_flat(p), force_scale=2.5)
+    out = torch.zeros((1000, 3), dtype=torch.float32, device=DEV)
+    cl.predict(to_dev_bits(bits), out)
+    y, _ = mlp.forward({k: v.astype(np.float64) for k, v in p.items()}, X, mirror=True)
+    err = rel_scale_err(out.cpu().numpy(), 2.5 * y)
+    print(f"[closure] forward rel err {err:.2e}", flush=True)
+    assert err < 2e-3
+    cl.close()
+
+
+def test_gradients_and_loss_match_oracle():
+    p = params_np(9)
+    rng = np.random.default_rng(2)
+    B = 777  # ragged: not a multiple of the 64-row tiles or of 256
+    X, bits = bf16_bits(rng.standard_normal((B, 256)))
+    F = rng.standard_normal((B, 3)).astype(np.float32)
+    scale = 1.7
+    cl = sph.Closure(scenes.mlp_flat(p), force_scale=scale)
+    g, loss = cl.gradient(to_dev_bits(bits), torch.from_numpy(F).to(DEV))
+    L, gref = mlp.loss_and_grads({k: v.astype(np.float64) for k, v in p.items()}, X, F / np.float32(scale))
+    assert loss == pytest.approx(L, rel=2e-3)
+    gd = scenes.mlp_unflat(g)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        err = rel_scale_err(gd[k].reshape(len(gd[k]), -1), gref[k].reshape(len(gref[k]), -1))
+        print(f"[closure] grad {k} rel err {err:.2e}", flush=True)
+        assert err < 2e-3, k
+    cl.close()
+
+
+def test_adam_step_matches_oracle():
+    p = params_np(11)
+    rng = np.random.default_rng(3)
+    cl = sph.Closure(scenes.mlp_flat(p))
+    ref = {k: v.astype(np.float64) for k, v in p.items()}
+    m = {k: np.zeros_like(v) for k, v in ref.items()}
+    v = {k: np.zeros_like(v) for k, v in ref.items()}
+    for t in range(1, 4):
+        g = (1e-2 * rng.standard_normal(sph.CLOSURE_PARAMS)).astype(np.float32)
+        cl.adam_step(g, t, lr=1e-3)
+        mlp.adam_step(ref, {k: val.astype(np.float64) for k, val in scenes.mlp_unflat(g).items()}, m, v, t, lr=1e-3)
+    w, _ = cl.weights()
+    np.testing.assert_allclose(w, scenes.mlp_flat({k: val.astype(np.float32) for k, val in ref.items()}),
+                               rtol=1e-5, atol=1e-8)
+    cl.close()
+
+
+def test_features_match_oracle():
+    sc = scenes.small_dam(nx=14, ny=10, nz=14, n_agents=40, agents="inside")
+    rng = np.random.default_rng(4)
+    v = (0.3 * rng.standard_normal(sc.x.shape)).astype(np.float32)
+    sim = sph.Simulation(sc.params, sc.x, v, sc.y, sc.u, flags=sph.FLAG_FEATURES)
+    sim.step(1)
+    f = sim.read(sph.AGENT_FEATURES)  # features of the state the step started from
+    dims, cell, inv, nc = oracle.grid(sc.params)
+    ref = mlp.features((dims, inv, sc.params["box_min"]), sc.x, v, sc.y, sc.u)
+    got = (f.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    # float32 vs float64 means may round to neighbouring bfloat16 values
+    ulp = np.maximum(np.abs(ref), 1e-30) * 2.0 ** -7
+    assert np.all(np.abs(got - ref) <= ulp + 1e-12)
+    assert np.mean(got == ref) > 0.99
+    sim.close()
+
+
+def _collect(sc, steps):
+    sim = sph.Simulation(sc.params, sc.x, sc.v, sc.y, sc.u, flags=sph.FLAG_FEATURES | sph.FLAG_DIAGNOSTICS)
+    feats, forces = [], []
+    for _ in range(steps):
+        sim.step(1)
+        feats.append(sim.read(sph.AGENT_FEATURES))
+        forces.append(sim.read(sph.AGENT_FORCE))
+    sim.close()
+    return np.concatenate(feats), np.concatenate(forces)
+
+
+def test_training_lowers_error_and_controller_switches():
+    sc = scenes.dam_break("agents", 24, 12, 24, 0.05, (0, 0, 0), (1.2, 0.6, 1.2), 4000, 5e-4, 10,
+                          scenes.SEED0 + 0x901, agents="inside")
+    feats, forces = _collect(sc, 6)
+    print(f"[closure] {len(feats)} training pairs", flush=True)
+    cl = sph.Closure(scenes.mlp_flat(scenes.mlp_init()))
+    F = torch.from_numpy(forces.astype(np.float32)).to(DEV)
+    X = to_dev_bits(feats)
+    rep0 = cl.train(X, F, epochs=0, batch=1024, val_fraction=0.2, seed=1)
+    rep = cl.train(X, F, epochs=30, batch=1024, val_fraction=0.2, seed=1)
+    print(f"[closure] untrained val rel rms {rep0['val_rel_rms']:.3f}, trained {rep['val_rel_rms']:.3f}", flush=True)
+    assert rep["val_rel_rms"] < 0.8 * rep0["val_rel_rms"]
+    # controller: a bound of 0 always falls back -> identical to the exact run
+    a = sph.create(sc)
+    a.attach_closure(cl, check_every=3, max_rel_rms=0.0)
+    a.step(7)
+    st = a.closure_stats()
+    assert st["checks"] == 3 and st["fallbacks"] == 3 and st["surrogate_steps"] == 0 and st["exact_steps"] == 7
+    b = sph.create(sc)
+    b.step(7)
+    for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL):
+        np.testing.assert_array_equal(a.read(f), b.read(f))
+    # an unbounded threshold switches to the surrogate after the first check
+    c = sph.create(sc)
+    c.attach_closure(cl, check_every=3, max_rel_rms=1e30)
+    c.step(7)
+    st = c.closure_stats()
+    assert st["mode"] == 1 and st["checks"] == 3 and st["surrogate_steps"] == 4 and st["exact_steps"] == 3
+    c.attach_closure(None)
+    for s in (a, b, c):
+        s.close()
+    cl.close()

@@ -1,0 +1,96 @@
+"""Execution forms of the step (per-phase launches, one fused persistent launch,
+kernel variants, tile widths, graphs, batched scenes) give bit-identical
+results, and the autotuner leaves the simulation state untouched."""
+import numpy as np
+import pytest
+
+import paper_2311_15088_amd as sph
+from paper_2311_15088_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def state(sim):
+    return [sim.read(f) for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL, sph.DENSITY, sph.NBR_COUNT)]
+
+
+def same(a, b):
+    for fa, fb in zip(a, b):
+        np.testing.assert_array_equal(fa, fb)
+
+
+def run(sc, steps, fused=0, variant=0, tile_x=16, graph=False, batch=None):
+    sim = sph.create_batch(batch) if batch is not None else sph.create(sc)
+    sim.set_tuning(fused, variant, tile_x)
+    if graph:
+        sim.capture(steps)
+    sim.step(steps)
+    out = state(sim)
+    sim.close()
+    return out
+
+
+def test_variants_and_tile_widths_are_bit_identical():
+    sc = scenes.small_dam(nx=20, ny=9, nz=15, n_agents=30, agents="inside")
+    print(f"[forms] n={sc.n}", flush=True)
+    ref = run(sc, 4)
+    for v in range(sph.variant_count(0)):
+        for tx in (1, 7, 16, 32):
+            same(ref, run(sc, 4, 0, v, tx))
+
+
+def test_fused_step_matches_per_phase_launches():
+    sc = scenes.config0c()
+    ref = run(sc, 6)
+    for v in range(sph.variant_count(1)):
+        for tx in (8, 16, 32):
+            print(f"[forms] fused variant {v} tile_x {tx}", flush=True)
+            same(ref, run(sc, 6, 1, v, tx))
+    same(ref, run(sc, 6, 1, 0, 16, graph=True))
+
+
+def test_fused_batched_matches_plain_per_scene():
+    specs = scenes.batched_specs(6, n_range=(300, 4000), a_range=(2, 40))
+    scs = [scenes.batched_scene(sp, k) for k, sp in enumerate(specs)]
+    bat = sph.create_batch(scs)
+    bat.set_tuning(1, 0, 16)
+    bat.capture(3)
+    bat.step(3)
+    X, V, Y, U = (bat.read(f) for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL))
+    for s, sc in enumerate(scs):
+        x, v, y, u, _, _ = run(sc, 3)
+        p0, p1 = bat.part_off[s], bat.part_off[s + 1]
+        a0, a1 = bat.agent_off[s], bat.agent_off[s + 1]
+        np.testing.assert_array_equal(X[p0:p1], x)
+        np.testing.assert_array_equal(V[p0:p1], v)
+        np.testing.assert_array_equal(Y[a0:a1], y)
+        np.testing.assert_array_equal(U[a0:a1], u)
+    bat.close()
+
+
+def test_autotune_keeps_state_and_picks_a_valid_form():
+    sc = scenes.small_dam(nx=24, ny=10, nz=20, n_agents=40, agents="inside")
+    a = sph.create(sc)
+    a.step(2)
+    before = state(a)
+    best = a.autotune(2)
+    print("[forms] autotune picked", best, flush=True)
+    assert best["ms_per_step"] > 0 and best["name"]
+    same(before, state(a))  # tuning did not advance the simulation
+    assert a.tuning()["fused"] == best["fused"] and a.tuning()["tile_x"] == best["tile_x"]
+    a.step(3)
+    b = sph.create(sc)
+    b.step(5)
+    same(state(a), state(b))
+    a.close()
+    b.close()
+
+
+def test_invalid_tuning_is_rejected():
+    sc = scenes.small_dam(nx=5, ny=5, nz=5, n_agents=2)
+    sim = sph.create(sc)
+    for bad in ((2, 0, 16), (0, 99, 16), (0, 0, 0), (0, 0, 64)):
+        with pytest.raises(sph.SphError) as ei:
+            sim.set_tuning(*bad)
+        assert ei.value.status == sph.EINVAL
+    sim.close()
