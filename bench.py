@@ -8,9 +8,12 @@ starts.  A step is one pass of the whole path: cell keys + counting sort,
 density, boid steering + coupling, forces + integration.
 
 Two regions run the same K steps from the same initial state:
-  * timed region: K steps with a HIP event recorded on the library's stream
-    after every kernel (per-kernel durations, the whole-step time);
-  * graph region: K steps replayed from captured HIP graphs (reported beside).
+  * timed region: K steps launched directly on the library's stream; the
+    density and force kernels carry HIP events recorded at their own start
+    and end, every other phase HIP events between launches (per-kernel
+    durations and the whole-step time; `value` comes from this region);
+  * graph region: K steps replayed from captured HIP graphs, without the
+    events (reported beside).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -30,6 +33,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed
+# dual issue) x 2.4 GHz.  This code is built without packed FP32, so half of
+# it (78.6 TFLOP/s) is the attainable ceiling; the published figure is the peak.
+PEAK_FP32_TFLOPS = 157.3
+
+# Algorithmic FP32 operations of the force + integration pass: per neighbour
+# pair (i, j in N_i) the pair term of the pressure and viscosity forces
+# (displacement 3, r^2 5, cut-off test 1, r, q, w 3, pressure coefficient 5,
+# velocity difference and viscosity coefficient 4, pair vector 13, sum 3), and
+# per particle the division by rho, coupling scale, gravity, Euler-Cromer
+# update and walls.
+FLOP_FORCE_PER_PAIR = 37
+FLOP_FORCE_PER_PARTICLE = 30
 
 # Algorithmic bytes per element and launch for each kernel of a step (the
 # arrays each kernel must read and write once, in the layout it uses).
@@ -85,7 +101,7 @@ def cpu_baseline(sc, budget_s: float):
         y, u = r["y1"].astype(np.float32), r["u1"].astype(np.float32)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 20:
+        if el >= budget_s or steps >= 200:
             break
     return {
         "value": steps * sc.n / el, "unit": "particle-steps/s", "cores": oracle.threads(), "kind": "oracle",
@@ -192,7 +208,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=25)
     ap.add_argument("--chunk", type=int, default=50, help="steps per captured graph in the graph region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -205,7 +221,26 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--closure-steps", type=int, default=1000)
     ap.add_argument("--headline-only", action="store_true")
+    ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times (calibrates the HBM "
+                         "byte counters of a profiler against a kernel of known traffic) and exit")
+    ap.add_argument("--plain-steps", type=int, default=0, metavar="N",
+                    help="only run N plain steps of the workload (no events, no graph) and exit: the command "
+                         "for profiler counter passes")
+    ap.add_argument("--tuning", default="", metavar="FUSED,VARIANT,TILE_X",
+                    help="execution form for --plain-steps (default: the library's)")
     args = ap.parse_args()
+    if args.copy_kernel:
+        import torch
+
+        nbytes = args.copy_kernel << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_kernel_bytes_read": nbytes, "copy_kernel_bytes_written": nbytes, "launches": 5}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the step is single-device).",
               file=sys.stderr)
@@ -219,6 +254,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     sc = scenes.config1()
+    if args.plain_steps:
+        sim = sph.create(sc)
+        if args.tuning:
+            sim.set_tuning(*[int(t) for t in args.tuning.split(",")])
+        sim.step(args.plain_steps)
+        torch.cuda.synchronize()
+        log(f"[bench] {args.plain_steps} plain steps done, tuning {sim.tuning()}")
+        sim.close()
+        return 0
     K, W = args.steps, args.warmup
     log(f"[bench] workload c1: n={sc.n} agents={sc.n_agents} steps={K} warmup={W}")
     dev = torch.device("cuda:0")
@@ -232,7 +276,7 @@ def main():
     # ---- timed region: K steps, HIP events after every kernel ----
     sim = make()
     info = sim.info()
-    sim.step(W)
+    sim.step_profiled(W)
     torch.cuda.synchronize()
     pairs0 = int(sim.read(sph.PAIR_COUNT)[0])
     torch.cuda.synchronize()
@@ -274,9 +318,13 @@ def main():
     # whole-step HBM fraction with B_alg = 154 + 24 C/N bytes per particle-step
     b_alg = 154.0 + 24.0 * cells / n
     hbm_frac_step = b_alg * n / (ms_per_step * 1e-3) / (PEAK_HBM_GBS * 1e9)
-    dom = max(phase_ms, key=phase_ms.get)
+    # roofline of the dominant kernel (force + integration): bound by vector
+    # ALU issue, not HBM (about 25 FP32 operations per byte it must move)
+    dom = "force_integrate"
     t_dom = phase_ms[dom] / K * 1e-3
-    ach = kernel_bytes(dom, n, cells, agents) / t_dom / 1e9
+    flop = (FLOP_FORCE_PER_PAIR * pairs / K + FLOP_FORCE_PER_PARTICLE * n)
+    ach = flop / t_dom / 1e12
+    ach_hbm = kernel_bytes(dom, n, cells, agents) / t_dom / 1e9
     result = {
         "metric": "particle-steps/s & %HBM roofline @1M SPH+boid; batched & surrogate vs plain",
         "value": value,
@@ -292,8 +340,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dam break 128x64x128 = 1,048,576 particles + 1,024 boids, h=0.02, dt=2e-4",
                    "n": n, "agents": agents, "cells": cells},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM_GBS, "traffic": None},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flop_per_launch": flop, "us_per_launch": t_dom * 1e6,
+                     "hbm_alg_GBs": ach_hbm, "hbm_alg_frac": ach_hbm / PEAK_HBM_GBS},
         "step_hbm_frac": hbm_frac_step,
         "b_alg_bytes_per_particle_step": b_alg,
         "pair_interactions_per_s": pairs / wall,

@@ -147,18 +147,21 @@ sph_status sph_info_get(const sph_ctx* ctx, sph_info* out);
 sph_status sph_capture(sph_ctx* ctx, int32_t n_steps);
 
 /* Execution form of a step, chosen by sph_autotune or set directly.
-   fused = 0: one launch per phase (variant = block size / LDS window of the
-   fluid passes); fused = 1: one persistent launch per step (variant = LDS
-   windows).  tile_x = grid cells per fluid tile along x (1..32).  Every form
-   gives bit-identical results; only the speed differs. */
+   fused = 0: one launch per phase (variant = block size / LDS capacity of
+   the fluid passes); fused = 1: one persistent launch per step (variant = LDS
+   capacities).  tile_x, tile_y, tile_z = the box of grid cells one workgroup
+   of the fluid passes takes at a time (each side 1..32, tile_y * tile_z <= 32,
+   8 (tile_x + 2)(tile_y + 2)(tile_z + 2) <= 1536).  Every form gives
+   bit-identical results; only the speed differs. */
 typedef struct sph_tuning {
-  int32_t fused, variant, tile_x;
+  int32_t fused, variant, tile_x, tile_y, tile_z;
   float ms_per_step; /* measured by sph_autotune (0 when set by hand) */
 } sph_tuning;
 
 /* Time steps_per_trial steps of every execution form on the context's own
-   state (the state is restored after each trial, so the simulation does not
-   advance), keep the fastest and store it in *best (may be NULL).  When the
+   state (two warm-up steps, then the faster of two timed runs; the state and
+   every readable field are restored after each trial, so the simulation does
+   not advance), keep the fastest and store it in *best (may be NULL).  When the
    environment variable SPH_AUTOTUNE_CACHE names a file, a result for the
    same device and problem shape is reused from it and new results appended.
    Drops a captured graph.  Synchronises the stream. */
@@ -236,12 +239,15 @@ const char* sph_closure_last_error(const sph_closure* cl);
 sph_status sph_closure_attach(sph_ctx* ctx, sph_closure* cl, int32_t check_every, float max_rel_rms);
 sph_status sph_closure_stats_get(sph_ctx* ctx, sph_closure_stats* out);
 
-/* Profiling: run n_steps steps eagerly (never from a captured graph),
-   recording a HIP event on the context's stream before the first kernel and
-   after every kernel; synchronises, then stores in phase_ms[p] the summed
-   duration in milliseconds of kernel p over the n_steps steps.  n_phases must
-   be >= SPH_STEP_PHASES; sph_phase_name(p) names kernel p. */
-#define SPH_STEP_PHASES 9
+/* Profiling: run n_steps steps launched directly (never from a captured
+   graph) and store in phase_ms[p] the summed duration in milliseconds of
+   phase p over the n_steps steps.  The density and force kernels are timed by
+   HIP events recorded at the kernel's own start and end (hipExtLaunchKernel);
+   every other phase by HIP events recorded on the context's stream before and
+   after it, which include the gap between launches.  Events are read back
+   every 25 steps while the next 25 run.  n_phases must be >=
+   SPH_STEP_PHASES; sph_phase_name(p) names phase p. */
+#define SPH_STEP_PHASES 10
 sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases);
 const char* sph_phase_name(int32_t phase);
 

@@ -66,11 +66,11 @@ class Tuning(ctypes.Structure):
     """Mirror of ``sph_tuning``."""
 
     _fields_ = [("fused", ctypes.c_int32), ("variant", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("ms_per_step", ctypes.c_float)]
+                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
 
     def as_dict(self):
-        return dict(fused=self.fused, variant=self.variant, tile_x=self.tile_x, ms_per_step=self.ms_per_step,
-                    name=variant_name(self.fused, self.variant))
+        return dict(fused=self.fused, variant=self.variant, tile=(self.tile_x, self.tile_y, self.tile_z),
+                    ms_per_step=self.ms_per_step, name=variant_name(self.fused, self.variant))
 
 
 class TrainParams(ctypes.Structure):
@@ -104,9 +104,14 @@ EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_
            "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
            "sph_closure_adam_step", "sph_closure_weights", "sph_closure_destroy", "sph_closure_last_error",
            "sph_closure_attach", "sph_closure_stats_get")
-STEP_PHASES = 9
+STEP_PHASES = 10
 
 _lib = None
+
+
+def phase_name(p: int) -> str:
+    """Name of kernel p of a step (0 <= p < STEP_PHASES)."""
+    return lib().sph_phase_name(int(p)).decode()
 
 
 def lib() -> ctypes.CDLL:
@@ -265,7 +270,8 @@ class Simulation:
         _check(lib().sph_capture(self._ctx, int(n)), self._ctx)
 
     def step_profiled(self, n: int) -> Dict[str, float]:
-        """Run n eager steps with HIP events around every kernel; summed ms per kernel."""
+        """Run n directly launched steps; summed ms per phase (density and force timed at the
+        kernels' own start and end, the other phases by events between launches)."""
         buf = (ctypes.c_double * STEP_PHASES)()
         _check(lib().sph_step_profiled(self._ctx, int(n), buf, STEP_PHASES), self._ctx)
         return {lib().sph_phase_name(p).decode(): buf[p] for p in range(STEP_PHASES)}
@@ -276,8 +282,10 @@ class Simulation:
         _check(lib().sph_autotune(self._ctx, int(steps_per_trial), ctypes.byref(t)), self._ctx)
         return t.as_dict()
 
-    def set_tuning(self, fused: int, variant: int, tile_x: int) -> None:
-        t = Tuning(int(fused), int(variant), int(tile_x), 0.0)
+    def set_tuning(self, fused: int, variant: int, tile=(4, 4, 2)) -> None:
+        """Execution form: fused (0/1), kernel variant, tile box (tx, ty, tz) of the fluid passes."""
+        tx, ty, tz = (int(v) for v in tile)
+        t = Tuning(int(fused), int(variant), tx, ty, tz, 0.0)
         _check(lib().sph_tuning_set(self._ctx, ctypes.byref(t)), self._ctx)
 
     def tuning(self) -> Dict:

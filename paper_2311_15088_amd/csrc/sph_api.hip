@@ -254,13 +254,21 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   }
   ctx->nsets = nsets;
   ctx->nchunks = chunk_prefix[nsets];
-  // tile width and kernel variant (SPH_TILE_X, SPH_FLUID_VARIANT override the defaults)
-  int tx = 16, variant = 0;
-  if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(kTXMax, atoi(e)));
+  // tile shape and kernel variant (SPH_TILE="tx,ty,tz" and SPH_FLUID_VARIANT
+  // override the defaults)
+  int tx = 4, ty = 4, tz = 2, variant = 0;
+  if (const char* e = getenv("SPH_TILE")) {
+    int a = 0, b = 0, c = 0;
+    if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && fluid_tile_shape_ok(a, b, c)) {
+      tx = a;
+      ty = b;
+      tz = c;
+    }
+  }
   if (const char* e = getenv("SPH_FLUID_VARIANT")) variant = std::max(0, std::min(fluid_variants() - 1, atoi(e)));
   std::vector<uint32_t> tprefix(S + 1, 0);
   for (int s = 0; s < S; ++s) {
-    const uint64_t t = (uint64_t)tprefix[s] + fluid_tiles(hs[s].g, 1);
+    const uint64_t t = (uint64_t)tprefix[s] + fluid_tiles(hs[s].g, 1, 1, 1);
     if (t >= (1ull << 31)) return fail(nullptr, SPH_ECAPACITY, "too many fluid tiles");
     tprefix[s + 1] = (uint32_t)t;
   }
@@ -276,7 +284,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->sx, N); ar.add(ctx->sy, N); ar.add(ctx->sz, N);
   ar.add(ctx->svx, N); ar.add(ctx->svy, N); ar.add(ctx->svz, N);
   ar.add(ctx->sid, N); ar.add(ctx->key, N); ar.add(ctx->rank, N); ar.add(ctx->tsrc, N); ar.add(ctx->tid, N);
-  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * N);
+  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 2 * N);
   ar.add(ctx->cnt, C); ar.add(ctx->off, C + S);
   ar.add(ctx->agx, A); ar.add(ctx->agy, A); ar.add(ctx->agz, A);
   ar.add(ctx->aux, A); ar.add(ctx->auy, A); ar.add(ctx->auz, A);
@@ -451,8 +459,10 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   P.ntiles = tprefix[S];
   P.tile_list = ctx->d_tile_list;
   P.tx = tx;
+  P.ty = ty;
+  P.tz = tz;
   P.variant = variant;
-  if (set_tiling(ctx, tx, variant) != SPH_OK) return bail(SPH_EHIP);
+  if (set_tiling(ctx, tx, ty, tz, variant) != SPH_OK) return bail(SPH_EHIP);
   if (ctx->features && sph_ctx_closure_buffers(ctx) != SPH_OK) return bail(SPH_ENOMEM);
   P.counters = ctx->d_counters;
   P.px = ctx->px; P.py = ctx->py; P.pz = ctx->pz;
@@ -472,19 +482,24 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   return SPH_OK;
 }
 
-// Tile width and kernel variant of the fluid passes.  The tile list is sized
-// for one-cell tiles, so any width fits.
-sph_status set_tiling(sph_ctx* ctx, int tx, int variant) {
-  if (tx < 1 || tx > kTXMax || variant < 0 || variant >= fluid_variants())
-    return fail(ctx, SPH_EINVAL, "tile width must be in [1, %d] and variant in [0, %d)", kTXMax, fluid_variants());
+// Tile shape and kernel variant of the fluid passes.  The tile list is sized
+// for one-cell tiles, so any shape fits.
+sph_status set_tiling(sph_ctx* ctx, int tx, int ty, int tz, int variant) {
+  if (!fluid_tile_shape_ok(tx, ty, tz) || variant < 0 || variant >= fluid_variants())
+    return fail(ctx, SPH_EINVAL,
+                "tile %dx%dx%d is not allowed (each side 1..%d, at most %d cells in y*z, halo of at most %d "
+                "half-cells) or variant not in [0, %d)",
+                tx, ty, tz, kTileMax, kOwnRowsMax, kNFCMax, fluid_variants());
   std::vector<uint32_t> tp(ctx->nscenes + 1, 0);
-  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx);
+  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx, ty, tz);
   // ordered after every kernel already enqueued on the stream that reads the old prefix
   hipError_t e = hipMemcpyAsync(ctx->d_tprefix, tp.data(), 4 * tp.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(ctx, SPH_EHIP, "tile prefix upload: %s", hipGetErrorString(e));
   ctx->phys.ntiles = tp[ctx->nscenes];
   ctx->phys.tx = tx;
+  ctx->phys.ty = ty;
+  ctx->phys.tz = tz;
   ctx->phys.variant = variant;
   return SPH_OK;
 }
@@ -525,6 +540,7 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
   } else {
     for (int32_t k = 0; k < n_steps; ++k) {
       launch_sort(ctx->sort, st);
+      launch_tile_list(ctx->phys, st);
       launch_density(ctx->phys, st);
       sph_ctx_closure_phase(ctx, st);
       launch_agents(ctx->phys, st);
@@ -537,58 +553,105 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
   return SPH_OK;
 }
 
-// Phase p of one step (p < kStepPhases), in launch order.
-static void launch_phase(sph_ctx* ctx, int p, hipStream_t st) {
+// Phase p of one step (p < kStepPhases), in launch order.  start / stop:
+// optional events at the fluid kernels' own start and end.
+static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
   if (p < kSortPhases) launch_sort_phase(ctx->sort, p, st);
-  else if (p == kSortPhases) launch_density(ctx->phys, st);
-  else if (p == kSortPhases + 1) {
+  else if (p == kSortPhases) launch_tile_list(ctx->phys, st);
+  else if (p == kSortPhases + 1) launch_density(ctx->phys, st, start, stop);
+  else if (p == kSortPhases + 2) {
     sph_ctx_closure_phase(ctx, st);
     launch_agents(ctx->phys, st);
   } else {
-    launch_force(ctx->phys, st);
+    launch_force(ctx->phys, st, start, stop);
     sph_ctx_closure_end(ctx, st);
   }
 }
 
+// Phases timed by events at their kernel's own start and end (the others by
+// events recorded on the stream between launches).
+static bool kernel_timed(int p) { return p == kSortPhases + 1 || p == kSortPhases + 3; }
+
+constexpr int kProfChunk = 25;                          // steps per set of events
+constexpr int kProfEvents = kStepPhases + 1 + 2 * 2;    // per step: markers, two start/stop pairs
+
+// Enqueue n steps with a marker event before the first phase and after every
+// phase, and start / stop events around the density and force kernels.
+static hipError_t enqueue_timed(sph_ctx* ctx, int n, const hipEvent_t* ev, hipStream_t st) {
+  hipError_t he = hipSuccess;
+  for (int s = 0; s < n && he == hipSuccess; ++s) {
+    const hipEvent_t* e = ev + (size_t)s * kProfEvents;
+    he = hipEventRecord(e[0], st);
+    int pair = 0;
+    for (int p = 0; p < kStepPhases && he == hipSuccess; ++p) {
+      if (kernel_timed(p)) {
+        launch_phase(ctx, p, st, e[kStepPhases + 1 + 2 * pair], e[kStepPhases + 2 + 2 * pair]);
+        ++pair;
+      } else {
+        launch_phase(ctx, p, st);
+      }
+      he = hipEventRecord(e[p + 1], st);
+    }
+  }
+  if (he == hipSuccess) he = hipGetLastError();
+  return he;
+}
+
+static sph_status add_elapsed(sph_ctx* ctx, int n, const hipEvent_t* ev, double* phase_ms) {
+  for (int s = 0; s < n; ++s) {
+    const hipEvent_t* e = ev + (size_t)s * kProfEvents;
+    int pair = 0;
+    for (int p = 0; p < kStepPhases; ++p) {
+      float ms = 0.0f;
+      hipError_t he;
+      if (kernel_timed(p)) {
+        he = ctx->phys.nf ? hipEventElapsedTime(&ms, e[kStepPhases + 1 + 2 * pair], e[kStepPhases + 2 + 2 * pair])
+                          : hipSuccess;
+        ++pair;
+      } else {
+        he = hipEventElapsedTime(&ms, e[p], e[p + 1]);
+      }
+      if (he != hipSuccess) return fail(ctx, SPH_EHIP, "hipEventElapsedTime: %s", hipGetErrorString(he));
+      phase_ms[p] += ms;
+    }
+  }
+  return SPH_OK;
+}
+
+// Steps are launched directly, kProfChunk at a time; two sets of events
+// alternate so the next chunk is queued before the previous one is read back.
 sph_status sph_profile_impl(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases) {
   if (n_phases < kStepPhases) return fail(ctx, SPH_EINVAL, "phase_ms must hold %d entries", kStepPhases);
   for (int p = 0; p < n_phases; ++p) phase_ms[p] = 0.0;
   if (n_steps <= 0) return SPH_OK;
   hipStream_t st = ctx->stream;
-  const int ne = n_steps * kStepPhases + 1;
-  std::vector<hipEvent_t> ev(ne, nullptr);
-  sph_status status = SPH_OK;
-  for (int k = 0; k < ne; ++k) {
-    if (hipEventCreate(&ev[k]) != hipSuccess) {
-      status = fail(ctx, SPH_EHIP, "hipEventCreate failed");
-      break;
+  const size_t ne = (size_t)kProfChunk * kProfEvents;
+  while (ctx->prof_ev.size() < 2 * ne) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return fail(ctx, SPH_EHIP, "hipEventCreate failed");
+    ctx->prof_ev.push_back(e);
+  }
+  int pending = -1, pending_n = 0;
+  for (int32_t done = 0; done < n_steps || pending >= 0;) {
+    int cur = -1, n = 0;
+    if (done < n_steps) {
+      cur = pending == 0 ? 1 : 0;
+      n = std::min<int32_t>(kProfChunk, n_steps - done);
+      hipError_t he = enqueue_timed(ctx, n, ctx->prof_ev.data() + cur * ne, st);
+      if (he != hipSuccess) return fail(ctx, SPH_EHIP, "profiled step: %s", hipGetErrorString(he));
+      done += n;
     }
+    if (pending >= 0) {
+      const hipEvent_t* ev = ctx->prof_ev.data() + pending * ne;
+      HIPCHK(hipEventSynchronize(ev[(size_t)(pending_n - 1) * kProfEvents + kStepPhases]));
+      sph_status s = add_elapsed(ctx, pending_n, ev, phase_ms);
+      if (s != SPH_OK) return s;
+      ctx->steps += pending_n;
+    }
+    pending = cur;
+    pending_n = n;
   }
-  if (status == SPH_OK) {
-    int e = 0;
-    hipError_t he = hipEventRecord(ev[e++], st);
-    for (int s = 0; s < n_steps && he == hipSuccess; ++s)
-      for (int p = 0; p < kStepPhases && he == hipSuccess; ++p) {
-        launch_phase(ctx, p, st);
-        he = hipEventRecord(ev[e++], st);
-      }
-    if (he == hipSuccess) he = hipGetLastError();
-    if (he == hipSuccess) he = hipEventSynchronize(ev[ne - 1]);
-    if (he != hipSuccess) status = fail(ctx, SPH_EHIP, "profiled step: %s", hipGetErrorString(he));
-    for (int s = 0; s < n_steps && status == SPH_OK; ++s)
-      for (int p = 0; p < kStepPhases; ++p) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev[s * kStepPhases + p], ev[s * kStepPhases + p + 1]) != hipSuccess) {
-          status = fail(ctx, SPH_EHIP, "hipEventElapsedTime failed");
-          break;
-        }
-        phase_ms[p] += ms;
-      }
-    if (status == SPH_OK) ctx->steps += n_steps;
-  }
-  for (auto e : ev)
-    if (e) (void)hipEventDestroy(e);
-  return status;
+  return SPH_OK;
 }
 
 __global__ void k_check_finite(const float* __restrict__ a, uint32_t n, int* flag) {
@@ -802,11 +865,12 @@ static sph_status drop_graph(sph_ctx* ctx) {
 
 static sph_status apply_tuning(sph_ctx* ctx, const sph_tuning& t) {
   const int nv = t.fused ? fused_variant_count() : fluid_variants();
-  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || t.tile_x < 1 || t.tile_x > kTXMax)
-    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile_x %d)", t.fused, t.variant, t.tile_x);
+  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || !fluid_tile_shape_ok(t.tile_x, t.tile_y, t.tile_z))
+    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile %dx%dx%d)", t.fused, t.variant, t.tile_x,
+                t.tile_y, t.tile_z);
   sph_status st = drop_graph(ctx);
   if (st != SPH_OK) return st;
-  st = set_tiling(ctx, t.tile_x, t.fused ? ctx->phys.variant : t.variant);
+  st = set_tiling(ctx, t.tile_x, t.tile_y, t.tile_z, t.fused ? ctx->phys.variant : t.variant);
   if (st != SPH_OK) return st;
   ctx->fused = t.fused != 0;
   if (t.fused) ctx->fused_variant = t.variant;
@@ -818,6 +882,8 @@ static void current_tuning(const sph_ctx* ctx, sph_tuning* t) {
   t->fused = ctx->fused ? 1 : 0;
   t->variant = ctx->fused ? ctx->fused_variant : ctx->phys.variant;
   t->tile_x = ctx->phys.tx;
+  t->tile_y = ctx->phys.ty;
+  t->tile_z = ctx->phys.tz;
   t->ms_per_step = ctx->tuned_ms;
 }
 
@@ -911,7 +977,8 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
       sph_tuning t;
       sph_tuning found{};
       bool hit = false;
-      while (fscanf(f, "%255s %d %d %d %f", k, &t.fused, &t.variant, &t.tile_x, &t.ms_per_step) == 5)
+      while (fscanf(f, "%255s %d %d %d %d %d %f", k, &t.fused, &t.variant, &t.tile_x, &t.tile_y, &t.tile_z,
+                    &t.ms_per_step) == 7)
         if (key == k) {
           found = t;
           hit = true;
@@ -931,22 +998,29 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
   best.ms_per_step = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<sph_tuning> cands;
-  const int txs[] = {8, 16, 32};
+  const int shapes[][3] = {{4, 4, 2}, {8, 2, 2}, {4, 2, 2}, {16, 1, 1}, {2, 2, 2}};
   for (int fused = 0; fused <= 1; ++fused)
     for (int v = 0; v < (fused ? fused_variant_count() : fluid_variants()); ++v)
-      for (int tx : txs) cands.push_back(sph_tuning{fused, v, tx, 0.0f});
+      for (const auto& sh : shapes) cands.push_back(sph_tuning{fused, v, sh[0], sh[1], sh[2], 0.0f});
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(ctx, SPH_EHIP, "event create");
   for (size_t c = 0; c < cands.size() && st == SPH_OK; ++c) {
     st = apply_tuning(ctx, cands[c]);
     if (st != SPH_OK) break;
-    st = sph_enqueue_steps(ctx, 1, ctx->stream);  // warm-up (first launch of a kernel)
+    st = sph_enqueue_steps(ctx, 2, ctx->stream);  // warm-up (first launches, clocks)
     if (st != SPH_OK) break;
-    hipError_t he = hipEventRecord(e0, ctx->stream);
-    if (he == hipSuccess) st = sph_enqueue_steps(ctx, steps, ctx->stream);
-    if (he == hipSuccess && st == SPH_OK) he = hipEventRecord(e1, ctx->stream);
-    if (he == hipSuccess && st == SPH_OK) he = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (he == hipSuccess && st == SPH_OK) he = hipEventElapsedTime(&ms, e0, e1);
+    // the faster of two timed runs: one slow run (a clock change, another
+    // process) does not decide the choice
+    float ms = 1e30f;
+    hipError_t he = hipSuccess;
+    for (int rep = 0; rep < 2 && he == hipSuccess && st == SPH_OK; ++rep) {
+      he = hipEventRecord(e0, ctx->stream);
+      if (he == hipSuccess) st = sph_enqueue_steps(ctx, steps, ctx->stream);
+      if (he == hipSuccess && st == SPH_OK) he = hipEventRecord(e1, ctx->stream);
+      if (he == hipSuccess && st == SPH_OK) he = hipEventSynchronize(e1);
+      float t = 0.0f;
+      if (he == hipSuccess && st == SPH_OK) he = hipEventElapsedTime(&t, e0, e1);
+      if (he == hipSuccess && st == SPH_OK) ms = std::min(ms, t);
+    }
     if (he != hipSuccess) st = fail(ctx, SPH_EHIP, "autotune trial: %s", hipGetErrorString(he));
     if (st != SPH_OK) break;
     int aborted = 0;
@@ -968,7 +1042,8 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
   if (cache && *cache) {
     FILE* f = fopen(cache, "a");
     if (f) {
-      fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), best.fused, best.variant, best.tile_x, best.ms_per_step);
+      fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), best.fused, best.variant, best.tile_x, best.tile_y,
+              best.tile_z, best.ms_per_step);
       fclose(f);
     }
   }
@@ -1064,7 +1139,7 @@ sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, in
 
 const char* sph_phase_name(int32_t phase) {
   static const char* names[kStepPhases] = {"key_count", "scan_reduce", "scan_sets", "scan_apply", "scatter",
-                                           "fixup_gather", "density", "agents", "force_integrate"};
+                                           "fixup_gather", "tile_list", "density", "agents", "force_integrate"};
   return (phase >= 0 && phase < kStepPhases) ? names[phase] : nullptr;
 }
 
@@ -1099,9 +1174,10 @@ sph_status sph_info_get(const sph_ctx* ctx, sph_info* out) {
 
 void sph_destroy(sph_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->stream || ctx->arena) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-  if (ctx->stream || ctx->arena) (void)hipStreamSynchronize(ctx->stream);
+  for (auto e : ctx->prof_ev) (void)hipEventDestroy(e);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->staging) (void)hipFree(ctx->staging);
   if (ctx->arena) (void)hipFree(ctx->arena);

@@ -68,6 +68,7 @@ struct sph_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int32_t graph_steps = 0;
+  std::vector<hipEvent_t> prof_ev;  // sph_step_profiled (created on first use)
 
   void* staging = nullptr;  // readback staging (allocated on first read)
   size_t staging_bytes = 0;
@@ -84,7 +85,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
                          const std::vector<const float*>& vel, const std::vector<const float*>& apos,
                          const std::vector<const float*>& avel, void* stream, sph_ctx** out);
 sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st);
-sph_status set_tiling(sph_ctx* ctx, int tx, int variant);
+sph_status set_tiling(sph_ctx* ctx, int tx, int ty, int tz, int variant);
 sph_status sph_ctx_closure_buffers(sph_ctx* ctx);
 void sph_ctx_closure_phase(sph_ctx* ctx, hipStream_t st);
 void sph_ctx_closure_end(sph_ctx* ctx, hipStream_t st);

@@ -8,11 +8,15 @@
 // Phase bodies are the same device functions the per-phase kernels run, in
 // the same order, so both forms give bit-identical results.
 //
-// Barrier: a counter and a generation word in device memory.  Arrivals are
-// agent-scope atomics with release/acquire fences (vector L1 written back /
-// invalidated around them).  A wait is bounded: after kSpinLimit polls the
-// block raises a sticky abort flag and leaves; every later barrier and every
-// later launch sees the flag and leaves at once, so the grid always drains.
+// Barrier: a counter and a generation word in device memory.  Each block
+// publishes its writes with one agent-scope release fence (the L2 of its XCD
+// is written back), arrives with a relaxed atomic, and waits by polling the
+// generation word with relaxed atomic loads; only after the wait does it take
+// one agent-scope acquire fence.  An acquire on every poll would invalidate
+// the XCD's L2 under the blocks that are still working.  A wait is bounded:
+// after kSpinLimit polls the block raises a sticky abort flag and leaves;
+// every later barrier and every later launch sees the flag and leaves at once,
+// so the grid always drains.
 #include "sph_api_internal.hpp"
 #include "sph_fluid_impl.hpp"
 #include "sph_sort_impl.hpp"
@@ -28,13 +32,15 @@ __device__ __forceinline__ bool grid_sync(uint32_t* bar, int* abort_flag, uint32
     int ok = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const uint32_t g = gen;
-    const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == gridDim.x - 1) {
+      // last arrival: reset the counter, then open the barrier (the release
+      // orders the reset before the new generation)
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++spins > kSpinLimit) {
           __hip_atomic_fetch_or(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
@@ -51,9 +57,17 @@ __device__ __forceinline__ bool grid_sync(uint32_t* bar, int* abort_flag, uint32
   return *s_ok != 0;
 }
 
+// LDS of the two fluid phases (never live at the same time).
+template <int CAPD, int CAPF>
+union FusedShared {
+  FluidShared<false, CAPD> d;
+  FluidShared<true, CAPF> f;
+};
+
 template <int CAPD, int CAPF>
 __global__ void __launch_bounds__(kFusedBD) k_step_fused(FusedPlan F) {
   __shared__ int s_ok;
+  __shared__ FusedShared<CAPD, CAPF> L;
   const SortPlan& S = F.sort;
   const PhysPlan& P = F.phys;
   const uint32_t G = gridDim.x;
@@ -77,14 +91,14 @@ __global__ void __launch_bounds__(kFusedBD) k_step_fused(FusedPlan F) {
   if (P.nf) {
     for (uint32_t b = blockIdx.x; b < (P.ntiles + 255) / 256; b += G) tile_list_block(P, b);
     if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
-    fluid_tiles<false, kFusedBD, CAPD>(P);
+    fluid_blocks<false, kFusedBD, CAPD>(P, L.d);
   }
   if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
   // agents and fluid forces touch disjoint arrays: no barrier between them
   const uint32_t agents_per_block = kFusedBD / kWave;
   for (uint32_t b = blockIdx.x; b < (P.na + agents_per_block - 1) / agents_per_block; b += G)
     agents_block<kFusedBD>(P, b);
-  if (P.nf) fluid_tiles<true, kFusedBD, CAPF>(P);
+  if (P.nf) fluid_blocks<true, kFusedBD, CAPF>(P, L.f);
 }
 
 using FusedFn = void (*)(FusedPlan);
@@ -96,9 +110,9 @@ struct FusedVariant {
 
 static const FusedVariant* fused_variants() {
   static const FusedVariant v[] = {
-      {(const void*)k_step_fused<512, 512>, "fused_win512_512"},
-      {(const void*)k_step_fused<1024, 512>, "fused_win1024_512"},
-      {(const void*)k_step_fused<256, 256>, "fused_win256_256"},
+      {(const void*)k_step_fused<2048, 1536>, "fused_cap2048_1536"},
+      {(const void*)k_step_fused<2048, 1280>, "fused_cap2048_1280"},
+      {(const void*)k_step_fused<1536, 1024>, "fused_cap1536_1024"},
   };
   return v;
 }

@@ -1,14 +1,17 @@
 // sph_physics.hip -- per-phase kernels of the fluid and agent passes and their
 // launch configurations; the bodies are in sph_fluid_impl.hpp.
+#include <hip/hip_ext.h>
+
 #include "sph_fluid_impl.hpp"
 
 namespace sph {
 
 __global__ void __launch_bounds__(256) k_tile_list(PhysPlan P) { tile_list_block(P, blockIdx.x); }
 
-template <bool FORCE, int BD, int CAP>
+template <bool FORCE, int BD, int CAPE>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
-  fluid_tiles<FORCE, BD, CAP>(P);
+  __shared__ FluidShared<FORCE, CAPE> L;
+  fluid_blocks<FORCE, BD, CAPE>(P, L);
 }
 
 template <int BD>
@@ -17,11 +20,11 @@ __global__ void __launch_bounds__(BD) k_agents(PhysPlan P) {
 }
 
 // ----------------------------------------------------------------------------
-// Launch configurations of the fluid passes: (block size, LDS window of the
-// density pass, of the force pass; a halo row longer than the window is
-// staged in pieces).  They are
-// instantiations of the one kernel above; every one produces bit-identical
-// results (the candidate order of each particle does not depend on them).
+// Launch configurations of the fluid passes: (block size, LDS capacity in
+// particles of the density pass, of the force pass).  A box whose halo holds
+// more particles than the capacity is done cell by cell.  Every variant
+// produces bit-identical results (a particle's candidate order and the
+// arithmetic on it do not depend on them).
 struct FluidVariant {
   const void* density;
   const void* force;
@@ -36,11 +39,11 @@ static FluidVariant make_variant(const char* name) {
 
 static const FluidVariant* variants() {
   static const FluidVariant v[] = {
-      make_variant<256, 512, 512>("bd256_win512_512"),
-      make_variant<128, 512, 256>("bd128_win512_256"),
-      make_variant<512, 512, 512>("bd512_win512_512"),
-      make_variant<256, 1024, 1024>("bd256_win1024_1024"),
-      make_variant<256, 256, 256>("bd256_win256_256"),
+      make_variant<256, 2048, 1536>("bd256_cap2048_1536"),
+      make_variant<256, 2048, 1280>("bd256_cap2048_1280"),
+      make_variant<128, 1024, 1024>("bd128_cap1024_1024"),
+      make_variant<512, 2048, 1536>("bd512_cap2048_1536"),
+      make_variant<256, 1536, 1024>("bd256_cap1536_1024"),
   };
   return v;
 }
@@ -63,7 +66,9 @@ static int persistent_blocks(const void* fn, int bd) {
   return ncu * per;
 }
 
-static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st) {
+// start / stop (may be null): events recorded when the kernel itself starts
+// and ends (hipExtLaunchKernel), without the gaps between launches.
+static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   static int grids[kNumVariants][2];
   const int v = (P.variant >= 0 && P.variant < kNumVariants) ? P.variant : 0;
   const FluidVariant& V = variants()[v];
@@ -72,18 +77,23 @@ static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st) {
   if (!grid) grid = persistent_blocks(fn, V.bd);
   const uint32_t g = std::min<uint32_t>((uint32_t)grid, P.ntiles);
   void* args[] = {(void*)&P};
-  (void)hipLaunchKernel(fn, dim3(g), dim3(V.bd), args, 0, st);
+  if (start || stop) (void)hipExtLaunchKernel(fn, dim3(g), dim3(V.bd), args, 0, st, start, stop, 0);
+  else (void)hipLaunchKernel(fn, dim3(g), dim3(V.bd), args, 0, st);
 }
 
-void launch_density(const PhysPlan& P, hipStream_t st) {
+void launch_tile_list(const PhysPlan& P, hipStream_t st) {
   if (!P.nf) return;
   hipLaunchKernelGGL(k_tile_list, dim3((P.ntiles + 255) / 256), dim3(256), 0, st, P);
-  launch_fluid(P, false, st);
 }
 
-void launch_force(const PhysPlan& P, hipStream_t st) {
+void launch_density(const PhysPlan& P, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
   if (!P.nf) return;
-  launch_fluid(P, true, st);
+  launch_fluid(P, false, st, start, stop);
+}
+
+void launch_force(const PhysPlan& P, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+  if (!P.nf) return;
+  launch_fluid(P, true, st, start, stop);
 }
 
 void launch_agents(const PhysPlan& P, hipStream_t st) {
@@ -93,6 +103,11 @@ void launch_agents(const PhysPlan& P, hipStream_t st) {
                      P);
 }
 
-uint32_t fluid_tiles(const DGrid& g, int tx) { return tiles_of(g, tx); }
+uint32_t fluid_tiles(const DGrid& g, int tx, int ty, int tz) { return tiles_of(g, tx, ty, tz); }
+
+bool fluid_tile_shape_ok(int tx, int ty, int tz) {
+  return tx >= 1 && ty >= 1 && tz >= 1 && tx <= kTileMax && ty <= kTileMax && tz <= kTileMax &&
+         tile_halo_halfcells(tx, ty, tz) <= kNFCMax && ty * tz <= kOwnRowsMax && (ty + 2) * (tz + 2) <= kHaloRowsMax;
+}
 
 }  // namespace sph

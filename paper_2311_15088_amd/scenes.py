@@ -256,6 +256,20 @@ def small_dam(nx=12, ny=10, nz=14, h=0.05, n_agents=24, agents="inside", seed=SE
     return dam_break("small", nx, ny, nz, h, (0, 0, 0), box_max, n_agents, dt, 5, seed, agents=agents)
 
 
+def clumped_dam(n_clump: int = 1500, side_cells: float = 2.0, seed: int = SEED0 + 0x778) -> Scene:
+    """small_dam plus a dense clump: n_clump extra particles uniform in a cube of
+    side_cells grid cells inside the fluid (a compressed region: cells far above
+    the rest occupancy, neighbour counts in the hundreds)."""
+    base = small_dam(seed=seed)
+    h = base.params["h"]
+    side = side_cells * h
+    centre = np.array([0.3, 0.2, 0.25])
+    extra = centre + uniform(seed, 3, n_clump, -0.5, 0.5) * side
+    x = _f32(np.concatenate([base.x.astype(np.float64), extra]))
+    v = np.zeros_like(x)
+    return Scene("clumped", base.params, x, v, base.y, base.u, base.steps)
+
+
 CONFIGS = {"c0": config0, "c0c": config0c, "c1": config1, "c2": config2, "c4": config4}
 
 

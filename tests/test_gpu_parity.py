@@ -73,6 +73,14 @@ def test_agents_above_and_upper():
     chained_parity(scenes.small_dam(nx=9, ny=9, nz=9, n_agents=50, agents="upper"), 2)
 
 
+def test_dense_clump_against_oracle():
+    """Cells with ~200 particles: neighbour counts in the hundreds, halos that
+    overflow LDS (cell-by-cell and global-memory paths), masks that overflow."""
+    sc = scenes.clumped_dam()
+    worst = chained_parity(sc, 2)
+    assert worst["rho"] < 1e-4
+
+
 def test_paper_literal_kernel_constants():
     sc = scenes.small_dam(nx=10, ny=8, nz=10, n_agents=12)
     sc.params["kernel_norm"] = 1
@@ -114,6 +122,24 @@ def test_graph_replay_equals_eager():
             np.testing.assert_array_equal(fa, fb)
         a.step(1)  # eager work between replays
         b.step(1)
+    a.close()
+    b.close()
+
+
+def test_profiled_steps_equal_plain_steps():
+    """sph_step_profiled (events read back every 25 steps) advances the state
+    exactly like sph_step."""
+    sc = scenes.config0c()
+    a = sph.create(sc)
+    b = sph.create(sc)
+    for n in (27, 3, 75):  # a chunk and a remainder, a remainder only, three chunks
+        a.step(n)
+        ph = b.step_profiled(n)
+        assert set(ph) == {sph.phase_name(p) for p in range(sph.STEP_PHASES)}
+        assert all(v > 0 for v in ph.values())
+        for fa, fb in zip(state(a), state(b)):
+            np.testing.assert_array_equal(fa, fb)
+    assert a.info()["steps"] == b.info()["steps"] == 105
     a.close()
     b.close()
 
