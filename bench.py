@@ -47,6 +47,24 @@ PEAK_FP32_TFLOPS = 157.3
 FLOP_FORCE_PER_PAIR = 37
 FLOP_FORCE_PER_PARTICLE = 30
 
+# HBM traffic of one force + integration launch from two rocprofv3 counter
+# runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scale factors a plain
+# 1 GiB device copy reads on the same counters; first 20 steps of this
+# workload), valid only for the kernel sources it was measured on.
+TRAFFIC_FORCE = {"sources_sha256_16": "b81040d89a62bc34", "bytes_per_launch": 341.3e6,
+                 "measured_on": "first 20 steps"}
+FORCE_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
+
+
+def force_traffic():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_FORCE["bytes_per_launch"] if h.hexdigest()[:16] == TRAFFIC_FORCE["sources_sha256_16"] else None
+
 # Algorithmic bytes per element and launch for each kernel of a step (the
 # arrays each kernel must read and write once, in the layout it uses).
 #   key_count      reads x,y,z (12), writes key, rank (8)             per particle
@@ -341,7 +359,8 @@ def main():
         "config": {"workload": "dam break 128x64x128 = 1,048,576 particles + 1,024 boids, h=0.02, dt=2e-4",
                    "n": n, "agents": agents, "cells": cells},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": ach / PEAK_FP32_TFLOPS, "traffic": force_traffic(),
+                     "traffic_unit": "bytes per launch", "traffic_measured_on": TRAFFIC_FORCE["measured_on"],
                      "flop_per_launch": flop, "us_per_launch": t_dom * 1e6,
                      "hbm_alg_GBs": ach_hbm, "hbm_alg_frac": ach_hbm / PEAK_HBM_GBS},
         "step_hbm_frac": hbm_frac_step,

@@ -147,14 +147,13 @@ sph_status sph_info_get(const sph_ctx* ctx, sph_info* out);
 sph_status sph_capture(sph_ctx* ctx, int32_t n_steps);
 
 /* Execution form of a step, chosen by sph_autotune or set directly.
-   fused = 0: one launch per phase (variant = block size / LDS capacity of
-   the fluid passes); fused = 1: one persistent launch per step (variant = LDS
-   capacities).  tile_x, tile_y, tile_z = the box of grid cells one workgroup
-   of the fluid passes takes at a time (each side 1..32, tile_y * tile_z <= 32,
-   8 (tile_x + 2)(tile_y + 2)(tile_z + 2) <= 1536).  Every form gives
-   bit-identical results; only the speed differs. */
+   fused = 0: one launch per phase (variant = block size / own particles per
+   thread / LDS capacity of the fluid passes); fused = 1: one persistent
+   launch per step (variant = LDS capacities).  tile_x = grid cells along x
+   that one workgroup of the fluid passes takes at a time (1..32).  Every form
+   gives bit-identical results; only the speed differs. */
 typedef struct sph_tuning {
-  int32_t fused, variant, tile_x, tile_y, tile_z;
+  int32_t fused, variant, tile_x;
   float ms_per_step; /* measured by sph_autotune (0 when set by hand) */
 } sph_tuning;
 

@@ -66,11 +66,11 @@ class Tuning(ctypes.Structure):
     """Mirror of ``sph_tuning``."""
 
     _fields_ = [("fused", ctypes.c_int32), ("variant", ctypes.c_int32), ("tile_x", ctypes.c_int32),
-                ("tile_y", ctypes.c_int32), ("tile_z", ctypes.c_int32), ("ms_per_step", ctypes.c_float)]
+                ("ms_per_step", ctypes.c_float)]
 
     def as_dict(self):
-        return dict(fused=self.fused, variant=self.variant, tile=(self.tile_x, self.tile_y, self.tile_z),
-                    ms_per_step=self.ms_per_step, name=variant_name(self.fused, self.variant))
+        return dict(fused=self.fused, variant=self.variant, tile_x=self.tile_x, ms_per_step=self.ms_per_step,
+                    name=variant_name(self.fused, self.variant))
 
 
 class TrainParams(ctypes.Structure):
@@ -282,10 +282,9 @@ class Simulation:
         _check(lib().sph_autotune(self._ctx, int(steps_per_trial), ctypes.byref(t)), self._ctx)
         return t.as_dict()
 
-    def set_tuning(self, fused: int, variant: int, tile=(4, 4, 2)) -> None:
-        """Execution form: fused (0/1), kernel variant, tile box (tx, ty, tz) of the fluid passes."""
-        tx, ty, tz = (int(v) for v in tile)
-        t = Tuning(int(fused), int(variant), tx, ty, tz, 0.0)
+    def set_tuning(self, fused: int, variant: int, tile_x: int = 32) -> None:
+        """Execution form: fused (0/1), kernel variant, cells per fluid tile along x."""
+        t = Tuning(int(fused), int(variant), int(tile_x), 0.0)
         _check(lib().sph_tuning_set(self._ctx, ctypes.byref(t)), self._ctx)
 
     def tuning(self) -> Dict:

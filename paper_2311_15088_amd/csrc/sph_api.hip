@@ -254,21 +254,13 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   }
   ctx->nsets = nsets;
   ctx->nchunks = chunk_prefix[nsets];
-  // tile shape and kernel variant (SPH_TILE="tx,ty,tz" and SPH_FLUID_VARIANT
-  // override the defaults)
-  int tx = 4, ty = 4, tz = 2, variant = 0;
-  if (const char* e = getenv("SPH_TILE")) {
-    int a = 0, b = 0, c = 0;
-    if (sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && fluid_tile_shape_ok(a, b, c)) {
-      tx = a;
-      ty = b;
-      tz = c;
-    }
-  }
+  // tile width and kernel variant (SPH_TILE_X, SPH_FLUID_VARIANT override the defaults)
+  int tx = 32, variant = 0;
+  if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(kTXMax, atoi(e)));
   if (const char* e = getenv("SPH_FLUID_VARIANT")) variant = std::max(0, std::min(fluid_variants() - 1, atoi(e)));
   std::vector<uint32_t> tprefix(S + 1, 0);
   for (int s = 0; s < S; ++s) {
-    const uint64_t t = (uint64_t)tprefix[s] + fluid_tiles(hs[s].g, 1, 1, 1);
+    const uint64_t t = (uint64_t)tprefix[s] + fluid_tiles(hs[s].g, 1);
     if (t >= (1ull << 31)) return fail(nullptr, SPH_ECAPACITY, "too many fluid tiles");
     tprefix[s + 1] = (uint32_t)t;
   }
@@ -284,7 +276,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->sx, N); ar.add(ctx->sy, N); ar.add(ctx->sz, N);
   ar.add(ctx->svx, N); ar.add(ctx->svy, N); ar.add(ctx->svz, N);
   ar.add(ctx->sid, N); ar.add(ctx->key, N); ar.add(ctx->rank, N); ar.add(ctx->tsrc, N); ar.add(ctx->tid, N);
-  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 2 * N);
+  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * N);
   ar.add(ctx->cnt, C); ar.add(ctx->off, C + S);
   ar.add(ctx->agx, A); ar.add(ctx->agy, A); ar.add(ctx->agz, A);
   ar.add(ctx->aux, A); ar.add(ctx->auy, A); ar.add(ctx->auz, A);
@@ -459,10 +451,8 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   P.ntiles = tprefix[S];
   P.tile_list = ctx->d_tile_list;
   P.tx = tx;
-  P.ty = ty;
-  P.tz = tz;
   P.variant = variant;
-  if (set_tiling(ctx, tx, ty, tz, variant) != SPH_OK) return bail(SPH_EHIP);
+  if (set_tiling(ctx, tx, variant) != SPH_OK) return bail(SPH_EHIP);
   if (ctx->features && sph_ctx_closure_buffers(ctx) != SPH_OK) return bail(SPH_ENOMEM);
   P.counters = ctx->d_counters;
   P.px = ctx->px; P.py = ctx->py; P.pz = ctx->pz;
@@ -482,24 +472,19 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   return SPH_OK;
 }
 
-// Tile shape and kernel variant of the fluid passes.  The tile list is sized
-// for one-cell tiles, so any shape fits.
-sph_status set_tiling(sph_ctx* ctx, int tx, int ty, int tz, int variant) {
-  if (!fluid_tile_shape_ok(tx, ty, tz) || variant < 0 || variant >= fluid_variants())
-    return fail(ctx, SPH_EINVAL,
-                "tile %dx%dx%d is not allowed (each side 1..%d, at most %d cells in y*z, halo of at most %d "
-                "half-cells) or variant not in [0, %d)",
-                tx, ty, tz, kTileMax, kOwnRowsMax, kNFCMax, fluid_variants());
+// Tile width and kernel variant of the fluid passes.  The tile list is sized
+// for one-cell tiles, so any width fits.
+sph_status set_tiling(sph_ctx* ctx, int tx, int variant) {
+  if (tx < 1 || tx > kTXMax || variant < 0 || variant >= fluid_variants())
+    return fail(ctx, SPH_EINVAL, "tile width must be in [1, %d] and variant in [0, %d)", kTXMax, fluid_variants());
   std::vector<uint32_t> tp(ctx->nscenes + 1, 0);
-  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx, ty, tz);
+  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx);
   // ordered after every kernel already enqueued on the stream that reads the old prefix
   hipError_t e = hipMemcpyAsync(ctx->d_tprefix, tp.data(), 4 * tp.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(ctx, SPH_EHIP, "tile prefix upload: %s", hipGetErrorString(e));
   ctx->phys.ntiles = tp[ctx->nscenes];
   ctx->phys.tx = tx;
-  ctx->phys.ty = ty;
-  ctx->phys.tz = tz;
   ctx->phys.variant = variant;
   return SPH_OK;
 }
@@ -865,12 +850,11 @@ static sph_status drop_graph(sph_ctx* ctx) {
 
 static sph_status apply_tuning(sph_ctx* ctx, const sph_tuning& t) {
   const int nv = t.fused ? fused_variant_count() : fluid_variants();
-  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || !fluid_tile_shape_ok(t.tile_x, t.tile_y, t.tile_z))
-    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile %dx%dx%d)", t.fused, t.variant, t.tile_x,
-                t.tile_y, t.tile_z);
+  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || t.tile_x < 1 || t.tile_x > kTXMax)
+    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile_x %d)", t.fused, t.variant, t.tile_x);
   sph_status st = drop_graph(ctx);
   if (st != SPH_OK) return st;
-  st = set_tiling(ctx, t.tile_x, t.tile_y, t.tile_z, t.fused ? ctx->phys.variant : t.variant);
+  st = set_tiling(ctx, t.tile_x, t.fused ? ctx->phys.variant : t.variant);
   if (st != SPH_OK) return st;
   ctx->fused = t.fused != 0;
   if (t.fused) ctx->fused_variant = t.variant;
@@ -882,8 +866,6 @@ static void current_tuning(const sph_ctx* ctx, sph_tuning* t) {
   t->fused = ctx->fused ? 1 : 0;
   t->variant = ctx->fused ? ctx->fused_variant : ctx->phys.variant;
   t->tile_x = ctx->phys.tx;
-  t->tile_y = ctx->phys.ty;
-  t->tile_z = ctx->phys.tz;
   t->ms_per_step = ctx->tuned_ms;
 }
 
@@ -977,8 +959,7 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
       sph_tuning t;
       sph_tuning found{};
       bool hit = false;
-      while (fscanf(f, "%255s %d %d %d %d %d %f", k, &t.fused, &t.variant, &t.tile_x, &t.tile_y, &t.tile_z,
-                    &t.ms_per_step) == 7)
+      while (fscanf(f, "%255s %d %d %d %f", k, &t.fused, &t.variant, &t.tile_x, &t.ms_per_step) == 5)
         if (key == k) {
           found = t;
           hit = true;
@@ -998,10 +979,10 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
   best.ms_per_step = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<sph_tuning> cands;
-  const int shapes[][3] = {{4, 4, 2}, {8, 2, 2}, {4, 2, 2}, {16, 1, 1}, {2, 2, 2}};
+  const int txs[] = {8, 16, 32};
   for (int fused = 0; fused <= 1; ++fused)
     for (int v = 0; v < (fused ? fused_variant_count() : fluid_variants()); ++v)
-      for (const auto& sh : shapes) cands.push_back(sph_tuning{fused, v, sh[0], sh[1], sh[2], 0.0f});
+      for (int tx : txs) cands.push_back(sph_tuning{fused, v, tx, 0.0f});
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(ctx, SPH_EHIP, "event create");
   for (size_t c = 0; c < cands.size() && st == SPH_OK; ++c) {
     st = apply_tuning(ctx, cands[c]);
@@ -1042,8 +1023,7 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
   if (cache && *cache) {
     FILE* f = fopen(cache, "a");
     if (f) {
-      fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), best.fused, best.variant, best.tile_x, best.tile_y,
-              best.tile_z, best.ms_per_step);
+      fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), best.fused, best.variant, best.tile_x, best.ms_per_step);
       fclose(f);
     }
   }

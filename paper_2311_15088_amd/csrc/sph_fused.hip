@@ -57,17 +57,9 @@ __device__ __forceinline__ bool grid_sync(uint32_t* bar, int* abort_flag, uint32
   return *s_ok != 0;
 }
 
-// LDS of the two fluid phases (never live at the same time).
-template <int CAPD, int CAPF>
-union FusedShared {
-  FluidShared<false, CAPD> d;
-  FluidShared<true, CAPF> f;
-};
-
 template <int CAPD, int CAPF>
 __global__ void __launch_bounds__(kFusedBD) k_step_fused(FusedPlan F) {
   __shared__ int s_ok;
-  __shared__ FusedShared<CAPD, CAPF> L;
   const SortPlan& S = F.sort;
   const PhysPlan& P = F.phys;
   const uint32_t G = gridDim.x;
@@ -91,14 +83,14 @@ __global__ void __launch_bounds__(kFusedBD) k_step_fused(FusedPlan F) {
   if (P.nf) {
     for (uint32_t b = blockIdx.x; b < (P.ntiles + 255) / 256; b += G) tile_list_block(P, b);
     if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
-    fluid_blocks<false, kFusedBD, CAPD>(P, L.d);
+    fluid_tiles<false, kFusedBD, CAPD>(P);
   }
   if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
   // agents and fluid forces touch disjoint arrays: no barrier between them
   const uint32_t agents_per_block = kFusedBD / kWave;
   for (uint32_t b = blockIdx.x; b < (P.na + agents_per_block - 1) / agents_per_block; b += G)
     agents_block<kFusedBD>(P, b);
-  if (P.nf) fluid_blocks<true, kFusedBD, CAPF>(P, L.f);
+  if (P.nf) fluid_tiles<true, kFusedBD, CAPF>(P);
 }
 
 using FusedFn = void (*)(FusedPlan);
@@ -110,9 +102,9 @@ struct FusedVariant {
 
 static const FusedVariant* fused_variants() {
   static const FusedVariant v[] = {
-      {(const void*)k_step_fused<2048, 1536>, "fused_cap2048_1536"},
-      {(const void*)k_step_fused<2048, 1280>, "fused_cap2048_1280"},
-      {(const void*)k_step_fused<1536, 1024>, "fused_cap1536_1024"},
+      {(const void*)k_step_fused<512, 512>, "fused_win512_512"},
+      {(const void*)k_step_fused<1024, 512>, "fused_win1024_512"},
+      {(const void*)k_step_fused<256, 256>, "fused_win256_256"},
   };
   return v;
 }

@@ -30,10 +30,7 @@ constexpr int kClStep = 0, kClMode = 1, kClUse = 2, kClCheck = 3, kClChecks = 4,
 
 constexpr int kWorkCounters = 3;
 constexpr int kCounterDensity = 0, kCounterForce = 1, kCounterList = 2;
-constexpr int kTileMax = 32;      // most cells per fluid tile along one axis
-constexpr int kNFCMax = 1536;      // half-cells of a tile's halo
-constexpr int kHaloRowsMax = 64;   // grid rows (y, z) of a tile's halo
-constexpr int kOwnRowsMax = 32;    // grid rows of a tile
+constexpr int kTXMax = 32;  // most cells per fluid tile
 
 // Device arrays of the physics kernels (all scenes concatenated).
 struct PhysPlan {
@@ -48,13 +45,13 @@ struct PhysPlan {
   const uint32_t* off;
   float* rho;
   uint32_t* nbr;
-  unsigned long long* nmask;   // [2][nf] 128-bit masks of each particle's neighbours among its candidates
+  unsigned long long* nmask;   // [9][nf] neighbours among each halo row's candidates (density -> force)
   unsigned long long* pairs;   // running sum of neighbour counts
-  // tiles: boxes of tx x ty x tz cells (all scenes concatenated)
+  // tiles: runs of tx cells along x in one grid row (all scenes concatenated)
   const uint32_t* tprefix;     // [nscenes + 1] tile prefix
   uint32_t ntiles;
-  int tx, ty, tz;              // tile shape in cells
-  int variant;                 // kernel variant (block size, LDS capacity per pass)
+  int tx;                      // cells per tile along x (<= kTXMax)
+  int variant;                 // kernel variant (block size, particles per thread, LDS capacity)
   uint32_t* tile_list;         // [ntiles] non-empty tiles of this step
   uint32_t* counters;          // [kWorkCounters]
   // fluid, next-step storage (written by the force kernel)
@@ -80,8 +77,7 @@ void launch_sort(const SortPlan& P, hipStream_t st);
 uint32_t scan_chunks(uint32_t ncells);
 
 constexpr int kStepPhases = kSortPhases + 4;  // + tile list, density, agents, force + integration
-uint32_t fluid_tiles(const DGrid& g, int tx, int ty, int tz);
-bool fluid_tile_shape_ok(int tx, int ty, int tz);
+uint32_t fluid_tiles(const DGrid& g, int tx);
 int fluid_variants();
 const char* fluid_variant_name(int v);
 void launch_tile_list(const PhysPlan& P, hipStream_t st);

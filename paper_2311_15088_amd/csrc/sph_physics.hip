@@ -8,10 +8,9 @@ namespace sph {
 
 __global__ void __launch_bounds__(256) k_tile_list(PhysPlan P) { tile_list_block(P, blockIdx.x); }
 
-template <bool FORCE, int BD, int CAPE>
+template <bool FORCE, int BD, int CAP>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
-  __shared__ FluidShared<FORCE, CAPE> L;
-  fluid_blocks<FORCE, BD, CAPE>(P, L);
+  fluid_tiles<FORCE, BD, CAP>(P);
 }
 
 template <int BD>
@@ -20,11 +19,11 @@ __global__ void __launch_bounds__(BD) k_agents(PhysPlan P) {
 }
 
 // ----------------------------------------------------------------------------
-// Launch configurations of the fluid passes: (block size, LDS capacity in
-// particles of the density pass, of the force pass).  A box whose halo holds
-// more particles than the capacity is done cell by cell.  Every variant
-// produces bit-identical results (a particle's candidate order and the
-// arithmetic on it do not depend on them).
+// Launch configurations of the fluid passes: (block size, LDS window of the
+// density pass, of the force pass; a halo row longer than the window is
+// staged in pieces).  They are instantiations of the one kernel above; every
+// one produces bit-identical results (the candidate order of each particle
+// does not depend on them).
 struct FluidVariant {
   const void* density;
   const void* force;
@@ -39,11 +38,11 @@ static FluidVariant make_variant(const char* name) {
 
 static const FluidVariant* variants() {
   static const FluidVariant v[] = {
-      make_variant<256, 2048, 1536>("bd256_cap2048_1536"),
-      make_variant<256, 2048, 1280>("bd256_cap2048_1280"),
-      make_variant<128, 1024, 1024>("bd128_cap1024_1024"),
-      make_variant<512, 2048, 1536>("bd512_cap2048_1536"),
-      make_variant<256, 1536, 1024>("bd256_cap1536_1024"),
+      make_variant<256, 512, 512>("bd256_win512_512"),
+      make_variant<128, 512, 256>("bd128_win512_256"),
+      make_variant<512, 512, 512>("bd512_win512_512"),
+      make_variant<256, 1024, 1024>("bd256_win1024_1024"),
+      make_variant<256, 256, 256>("bd256_win256_256"),
   };
   return v;
 }
@@ -103,11 +102,6 @@ void launch_agents(const PhysPlan& P, hipStream_t st) {
                      P);
 }
 
-uint32_t fluid_tiles(const DGrid& g, int tx, int ty, int tz) { return tiles_of(g, tx, ty, tz); }
-
-bool fluid_tile_shape_ok(int tx, int ty, int tz) {
-  return tx >= 1 && ty >= 1 && tz >= 1 && tx <= kTileMax && ty <= kTileMax && tz <= kTileMax &&
-         tile_halo_halfcells(tx, ty, tz) <= kNFCMax && ty * tz <= kOwnRowsMax && (ty + 2) * (tz + 2) <= kHaloRowsMax;
-}
+uint32_t fluid_tiles(const DGrid& g, int tx) { return tiles_of(g, tx); }
 
 }  // namespace sph

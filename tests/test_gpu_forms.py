@@ -19,12 +19,12 @@ def same(a, b):
         np.testing.assert_array_equal(fa, fb)
 
 
-SHAPES = ((4, 4, 2), (1, 1, 1), (8, 2, 2), (16, 1, 1), (2, 2, 2), (3, 5, 2), (14, 1, 1))
+WIDTHS = (32, 1, 7, 16, 8)
 
 
-def run(sc, steps, fused=0, variant=0, tile=(4, 4, 2), graph=False, batch=None):
+def run(sc, steps, fused=0, variant=0, tile_x=32, graph=False, batch=None):
     sim = sph.create_batch(batch) if batch is not None else sph.create(sc)
-    sim.set_tuning(fused, variant, tile)
+    sim.set_tuning(fused, variant, tile_x)
     if graph:
         sim.capture(steps)
     sim.step(steps)
@@ -33,46 +33,46 @@ def run(sc, steps, fused=0, variant=0, tile=(4, 4, 2), graph=False, batch=None):
     return out
 
 
-def test_variants_and_tile_shapes_are_bit_identical():
+def test_variants_and_tile_widths_are_bit_identical():
     sc = scenes.small_dam(nx=20, ny=9, nz=15, n_agents=30, agents="inside")
     print(f"[forms] n={sc.n}", flush=True)
     ref = run(sc, 4)
     for v in range(sph.variant_count(0)):
-        for tile in SHAPES:
-            same(ref, run(sc, 4, 0, v, tile))
+        for tx in WIDTHS:
+            same(ref, run(sc, 4, 0, v, tx))
 
 
 def test_dense_clump_takes_every_path_bit_identically():
-    """A clump of ~200 particles per cell: tile halos overflow LDS (cell-by-cell
-    fallback), 27-cell halos overflow the smaller capacities (global-memory
-    path), and candidates beyond the 128 recorded in a mask are tested in the
-    force pass.  Every variant and shape must agree bit for bit."""
+    """A clump of ~200 particles per cell: halo rows longer than every LDS
+    window (staged in pieces) and rows with more candidates than a 64-bit mask
+    records (retested in the force pass).  Every variant and width must agree
+    bit for bit."""
     sc = scenes.clumped_dam()
     print(f"[forms] clump n={sc.n}", flush=True)
     ref = run(sc, 2)
     for v in range(sph.variant_count(0)):
-        for tile in ((4, 4, 2), (1, 1, 1), (16, 1, 1)):
-            print(f"[forms] clump variant {v} tile {tile}", flush=True)
-            same(ref, run(sc, 2, 0, v, tile))
+        for tx in (32, 1, 5):
+            print(f"[forms] clump variant {v} tile_x {tx}", flush=True)
+            same(ref, run(sc, 2, 0, v, tx))
     for v in range(sph.variant_count(1)):
-        same(ref, run(sc, 2, 1, v, (4, 4, 2)))
+        same(ref, run(sc, 2, 1, v, 32))
 
 
 def test_fused_step_matches_per_phase_launches():
     sc = scenes.config0c()
     ref = run(sc, 6)
     for v in range(sph.variant_count(1)):
-        for tile in ((4, 4, 2), (8, 2, 2), (16, 1, 1)):
-            print(f"[forms] fused variant {v} tile {tile}", flush=True)
-            same(ref, run(sc, 6, 1, v, tile))
-    same(ref, run(sc, 6, 1, 0, (4, 4, 2), graph=True))
+        for tx in (32, 8, 13):
+            print(f"[forms] fused variant {v} tile_x {tx}", flush=True)
+            same(ref, run(sc, 6, 1, v, tx))
+    same(ref, run(sc, 6, 1, 0, 32, graph=True))
 
 
 def test_fused_batched_matches_plain_per_scene():
     specs = scenes.batched_specs(6, n_range=(300, 4000), a_range=(2, 40))
     scs = [scenes.batched_scene(sp, k) for k, sp in enumerate(specs)]
     bat = sph.create_batch(scs)
-    bat.set_tuning(1, 0, (4, 4, 2))
+    bat.set_tuning(1, 0, 32)
     bat.capture(3)
     bat.step(3)
     X, V, Y, U = (bat.read(f) for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL))
@@ -96,7 +96,7 @@ def test_autotune_keeps_state_and_picks_a_valid_form():
     print("[forms] autotune picked", best, flush=True)
     assert best["ms_per_step"] > 0 and best["name"]
     same(before, state(a))  # tuning did not advance the simulation
-    assert a.tuning()["fused"] == best["fused"] and a.tuning()["tile"] == best["tile"]
+    assert a.tuning()["fused"] == best["fused"] and a.tuning()["tile_x"] == best["tile_x"]
     a.step(3)
     b = sph.create(sc)
     b.step(5)
@@ -108,8 +108,7 @@ def test_autotune_keeps_state_and_picks_a_valid_form():
 def test_invalid_tuning_is_rejected():
     sc = scenes.small_dam(nx=5, ny=5, nz=5, n_agents=2)
     sim = sph.create(sc)
-    for bad in ((2, 0, (4, 4, 2)), (0, 99, (4, 4, 2)), (0, 0, (0, 1, 1)), (0, 0, (64, 1, 1)), (0, 0, (32, 1, 1)),
-                (0, 0, (1, 33, 1))):
+    for bad in ((2, 0, 16), (0, 99, 16), (0, 0, 0), (0, 0, 33), (1, 99, 8)):
         with pytest.raises(sph.SphError) as ei:
             sim.set_tuning(*bad)
         assert ei.value.status == sph.EINVAL

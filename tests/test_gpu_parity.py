@@ -74,8 +74,8 @@ def test_agents_above_and_upper():
 
 
 def test_dense_clump_against_oracle():
-    """Cells with ~200 particles: neighbour counts in the hundreds, halos that
-    overflow LDS (cell-by-cell and global-memory paths), masks that overflow."""
+    """Cells with ~200 particles: neighbour counts in the hundreds, halo rows
+    staged in several LDS windows, rows whose candidates overflow a mask."""
     sc = scenes.clumped_dam()
     worst = chained_parity(sc, 2)
     assert worst["rho"] < 1e-4
