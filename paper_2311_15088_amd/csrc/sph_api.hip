@@ -255,7 +255,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ctx->nsets = nsets;
   ctx->nchunks = chunk_prefix[nsets];
   // tile width and kernel variant (SPH_TILE_X, SPH_FLUID_VARIANT override the defaults)
-  int tx = 32, variant = 0;
+  int tx = 24, variant = 0;
   if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(kTXMax, atoi(e)));
   if (const char* e = getenv("SPH_FLUID_VARIANT")) variant = std::max(0, std::min(fluid_variants() - 1, atoi(e)));
   std::vector<uint32_t> tprefix(S + 1, 0);
@@ -276,7 +276,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->sx, N); ar.add(ctx->sy, N); ar.add(ctx->sz, N);
   ar.add(ctx->svx, N); ar.add(ctx->svy, N); ar.add(ctx->svz, N);
   ar.add(ctx->sid, N); ar.add(ctx->key, N); ar.add(ctx->rank, N); ar.add(ctx->tsrc, N); ar.add(ctx->tid, N);
-  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * N);
+  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * 6 * N);
   ar.add(ctx->cnt, C); ar.add(ctx->off, C + S);
   ar.add(ctx->agx, A); ar.add(ctx->agy, A); ar.add(ctx->agz, A);
   ar.add(ctx->aux, A); ar.add(ctx->auy, A); ar.add(ctx->auz, A);
@@ -453,6 +453,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   P.tx = tx;
   P.variant = variant;
   if (set_tiling(ctx, tx, variant) != SPH_OK) return bail(SPH_EHIP);
+  P.item_max = (uint32_t)fluid_item_max(ctx->fused ? 1 : 0, ctx->fused ? ctx->fused_variant : variant);
   if (ctx->features && sph_ctx_closure_buffers(ctx) != SPH_OK) return bail(SPH_ENOMEM);
   P.counters = ctx->d_counters;
   P.px = ctx->px; P.py = ctx->py; P.pz = ctx->pz;
@@ -858,6 +859,7 @@ static sph_status apply_tuning(sph_ctx* ctx, const sph_tuning& t) {
   if (st != SPH_OK) return st;
   ctx->fused = t.fused != 0;
   if (t.fused) ctx->fused_variant = t.variant;
+  ctx->phys.item_max = (uint32_t)fluid_item_max(t.fused, t.variant);
   ctx->tuned_ms = t.ms_per_step;
   return SPH_OK;
 }

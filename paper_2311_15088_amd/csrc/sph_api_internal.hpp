@@ -32,7 +32,7 @@ struct sph_ctx {
   uint32_t *sid, *key, *rank, *tsrc, *tid;
   float* rho;
   uint32_t* nbr;
-  unsigned long long* nmask;
+  uint32_t* nmask;
   uint32_t *cnt, *off;
   // agents: state (id order), cell-ordered copies, scratch
   float *agx, *agy, *agz, *aux, *auy, *auz;
@@ -50,7 +50,7 @@ struct sph_ctx {
   unsigned long long* d_pairs;
   uint32_t* d_tprefix;
   uint32_t* d_counters;
-  uint32_t* d_tile_list;
+  unsigned long long* d_tile_list;
   uint32_t ntiles = 0;
   int* d_flag;
   int nsets = 0;

@@ -45,14 +45,15 @@ struct PhysPlan {
   const uint32_t* off;
   float* rho;
   uint32_t* nbr;
-  unsigned long long* nmask;   // [9][nf] neighbours among each halo row's candidates (density -> force)
+  uint32_t* nmask;             // [9][6][nf] neighbours among each halo row's candidates, 32 per word (density -> force)
   unsigned long long* pairs;   // running sum of neighbour counts
   // tiles: runs of tx cells along x in one grid row (all scenes concatenated)
   const uint32_t* tprefix;     // [nscenes + 1] tile prefix
   uint32_t ntiles;
   int tx;                      // cells per tile along x (<= kTXMax)
   int variant;                 // kernel variant (block size, particles per thread, LDS capacity)
-  uint32_t* tile_list;         // [ntiles] non-empty tiles of this step
+  unsigned long long* tile_list;  // [cells] work items of this step (tile << 16 | first cell << 8 | last cell)
+  uint32_t item_max;           // particles per work item before a tile is cut
   uint32_t* counters;          // [kWorkCounters]
   // fluid, next-step storage (written by the force kernel)
   float *px, *py, *pz, *vx, *vy, *vz;
@@ -79,6 +80,8 @@ uint32_t scan_chunks(uint32_t ncells);
 constexpr int kStepPhases = kSortPhases + 4;  // + tile list, density, agents, force + integration
 uint32_t fluid_tiles(const DGrid& g, int tx);
 int fluid_variants();
+// particles per work item of the fluid passes: the block size of the form
+int fluid_item_max(int fused, int variant);
 const char* fluid_variant_name(int v);
 void launch_tile_list(const PhysPlan& P, hipStream_t st);
 // start / stop: optional events recorded at the fluid kernel's own start and end

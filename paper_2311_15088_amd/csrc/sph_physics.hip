@@ -50,6 +50,11 @@ constexpr int kNumVariants = 5;
 constexpr int kAgentBD = 256;
 
 int fluid_variants() { return kNumVariants; }
+
+int fluid_item_max(int fused, int variant) {
+  if (fused) return kFusedBD;
+  return variants()[(variant >= 0 && variant < kNumVariants) ? variant : 0].bd;
+}
 const char* fluid_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? variants()[v].name : nullptr; }
 
 static int persistent_blocks(const void* fn, int bd) {
