@@ -69,7 +69,6 @@ def force_traffic():
 # arrays each kernel must read and write once, in the layout it uses).
 #   key_count      reads x,y,z (12), writes key, rank (8)             per particle
 #   scan_reduce    reads cnt (4)                                       per cell
-#   scan_sets      reads / writes chunk sums (8)                       per 4,096 cells
 #   scan_apply     reads cnt (4), writes off (4), clears cnt (4)       per cell
 #   scatter        reads key, rank, id (12), writes src, id (8)        per particle
 #   fixup_gather   reads src, id, key (12), x, v (24), writes x, v, id (28) per particle
@@ -89,8 +88,6 @@ def kernel_bytes(name, n, cells, agents):
         return B_PER_PARTICLE[name] * n
     if name in B_PER_CELL:
         return B_PER_CELL[name] * cells
-    if name == "scan_sets":
-        return 8 * math.ceil(cells / 4096)
     if name == "agents":
         return 48 * agents
     return 0

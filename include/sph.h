@@ -246,7 +246,7 @@ sph_status sph_closure_stats_get(sph_ctx* ctx, sph_closure_stats* out);
    after it, which include the gap between launches.  Events are read back
    every 25 steps while the next 25 run.  n_phases must be >=
    SPH_STEP_PHASES; sph_phase_name(p) names phase p. */
-#define SPH_STEP_PHASES 10
+#define SPH_STEP_PHASES 9
 sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases);
 const char* sph_phase_name(int32_t phase);
 

@@ -1120,8 +1120,8 @@ sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, in
 }
 
 const char* sph_phase_name(int32_t phase) {
-  static const char* names[kStepPhases] = {"key_count", "scan_reduce", "scan_sets", "scan_apply", "scatter",
-                                           "fixup_gather", "tile_list", "density", "agents", "force_integrate"};
+  static const char* names[kStepPhases] = {"key_count", "scan_reduce", "scan_apply", "scatter", "fixup_gather",
+                                           "tile_list", "density", "agents", "force_integrate"};
   return (phase >= 0 && phase < kStepPhases) ? names[phase] : nullptr;
 }
 

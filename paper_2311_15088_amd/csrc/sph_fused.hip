@@ -70,9 +70,8 @@ __global__ void __launch_bounds__(kFusedBD) k_step_fused(FusedPlan F) {
 
   for (uint32_t b = blockIdx.x; b < S.nblocks; b += G) key_count_block(S.sets, S.nsets, S.bprefix, b);
   if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
-  for (uint32_t b = blockIdx.x; b < S.nchunks; b += G) scan_reduce_block(S.sets, S.nsets, S.chunk_prefix, S.bsum, b);
-  if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
-  for (uint32_t b = blockIdx.x; b < (uint32_t)S.nsets; b += G) scan_sets_block(S.nsets, S.chunk_prefix, S.bsum, S.counters, b);
+  for (uint32_t b = blockIdx.x; b < S.nchunks; b += G)
+    scan_reduce_block(S.sets, S.nsets, S.chunk_prefix, S.bsum, S.counters, b);
   if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;
   for (uint32_t b = blockIdx.x; b < S.nchunks; b += G) scan_apply_block(S.sets, S.nsets, S.chunk_prefix, S.bsum, b);
   if (!grid_sync(F.bar, F.abort_flag, gen, &s_ok)) return;

@@ -72,7 +72,7 @@ struct PhysPlan {
   uint32_t *d_touch, *d_acnt;                   // [n] / [a][4]
 };
 
-constexpr int kSortPhases = 6;  // key+count, scan reduce, scan sets, scan apply, scatter, fix-up
+constexpr int kSortPhases = 5;  // key+count, scan reduce, scan apply, scatter, fix-up
 void launch_sort_phase(const SortPlan& P, int phase, hipStream_t st);
 void launch_sort(const SortPlan& P, hipStream_t st);
 uint32_t scan_chunks(uint32_t ncells);

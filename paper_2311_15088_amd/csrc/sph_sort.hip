@@ -10,12 +10,8 @@ __global__ void __launch_bounds__(kSortBD) k_key_count(const SortSet* __restrict
 }
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const SortSet* __restrict__ sets, int nsets,
                                                               const uint32_t* __restrict__ chunk_prefix,
-                                                              uint32_t* __restrict__ bsum) {
-  scan_reduce_block(sets, nsets, chunk_prefix, bsum, blockIdx.x);
-}
-__global__ void __launch_bounds__(kScanThreads) k_scan_sets(int nsets, const uint32_t* __restrict__ chunk_prefix,
-                                                            uint32_t* __restrict__ bsum, uint32_t* counters) {
-  scan_sets_block(nsets, chunk_prefix, bsum, counters, blockIdx.x);
+                                                              uint32_t* __restrict__ bsum, uint32_t* counters) {
+  scan_reduce_block(sets, nsets, chunk_prefix, bsum, counters, blockIdx.x);
 }
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const SortSet* __restrict__ sets, int nsets,
                                                              const uint32_t* __restrict__ chunk_prefix,
@@ -37,19 +33,16 @@ void launch_sort_phase(const SortPlan& P, int phase, hipStream_t st) {
       if (P.nblocks) hipLaunchKernelGGL(k_key_count, dim3(P.nblocks), dim3(kSortBD), 0, st, P.sets, P.nsets, P.bprefix);
       break;
     case 1:
-      hipLaunchKernelGGL(k_scan_reduce, dim3(P.nchunks), dim3(kScanThreads), 0, st, P.sets, P.nsets, P.chunk_prefix, P.bsum);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_scan_sets, dim3(P.nsets), dim3(kScanThreads), 0, st, P.nsets, P.chunk_prefix, P.bsum,
+      hipLaunchKernelGGL(k_scan_reduce, dim3(P.nchunks), dim3(kScanThreads), 0, st, P.sets, P.nsets, P.chunk_prefix, P.bsum,
                          P.counters);
       break;
-    case 3:
+    case 2:
       hipLaunchKernelGGL(k_scan_apply, dim3(P.nchunks), dim3(kScanThreads), 0, st, P.sets, P.nsets, P.chunk_prefix, P.bsum);
       break;
-    case 4:
+    case 3:
       if (P.nblocks) hipLaunchKernelGGL(k_scatter, dim3(P.nblocks), dim3(kSortBD), 0, st, P.sets, P.nsets, P.bprefix);
       break;
-    case 5:
+    case 4:
       if (P.nblocks) hipLaunchKernelGGL(k_fixup, dim3(P.nblocks), dim3(kSortBD), 0, st, P.sets, P.nsets, P.bprefix);
       break;
   }

@@ -81,12 +81,14 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
   return woff + inc - v;
 }
 
-// Phase 1: per-chunk totals (coalesced loads).
+// Phase 1: per-chunk totals (coalesced loads); block 0 also clears the work
+// counters of this step's tiled passes.
 __device__ __forceinline__ void scan_reduce_block(const SortSet* __restrict__ sets, int nsets,
-                                                              const uint32_t* __restrict__ chunk_prefix,
-                                                              uint32_t* __restrict__ bsum, uint32_t blk) {
+                                                  const uint32_t* __restrict__ chunk_prefix,
+                                                  uint32_t* __restrict__ bsum, uint32_t* counters, uint32_t blk) {
   __shared__ uint32_t lw[kScanThreads / kWave];
   const uint32_t b = blk;
+  if (b == 0 && threadIdx.x < kWorkCounters && counters) counters[threadIdx.x] = 0u;
   const int s = (int)uni(find_set(chunk_prefix, nsets, b));
   const SortSet& S = sets[s];
   const uint32_t c0 = (b - chunk_prefix[s]) * kChunk;
@@ -101,29 +103,10 @@ __device__ __forceinline__ void scan_reduce_block(const SortSet* __restrict__ se
   if (threadIdx.x == 0) bsum[b] = tot;
 }
 
-// Phase 2: exclusive scan of the chunk totals of each set (one block per set);
-// also clears the work counters of this step's tiled passes.
-__device__ __forceinline__ void scan_sets_block(int nsets, const uint32_t* __restrict__ chunk_prefix,
-                                                            uint32_t* __restrict__ bsum, uint32_t* counters, uint32_t blk) {
-  __shared__ uint32_t lw[kScanThreads / kWave];
-  const int s = blk;
-  if (s == 0 && threadIdx.x < kWorkCounters && counters) counters[threadIdx.x] = 0u;
-  if (s >= nsets) return;
-  const uint32_t b0 = chunk_prefix[s], b1 = chunk_prefix[s + 1];
-  uint32_t carry = 0;
-  for (uint32_t base = b0; base < b1; base += kScanThreads) {
-    uint32_t b = base + threadIdx.x;
-    uint32_t v = (b < b1) ? bsum[b] : 0u;
-    uint32_t tot;
-    uint32_t ex = block_exclusive_scan(v, lw, tot);
-    if (b < b1) bsum[b] = carry + ex;
-    carry += tot;
-  }
-}
-
-// Phase 3: offsets of every cell; clears the counters; writes off[cells] = n.
-// Coalesced loads/stores, transposed through LDS so that every thread scans
-// kScanPer consecutive cells.
+// Phase 2: offsets of every cell; clears the counters; writes off[cells] = n.
+// A chunk's base is the sum of the totals of the set's earlier chunks, summed
+// by the block itself.  Coalesced loads/stores, transposed through LDS so
+// that every thread scans kScanPer consecutive cells.
 __device__ __forceinline__ void scan_apply_block(const SortSet* __restrict__ sets, int nsets,
                                                              const uint32_t* __restrict__ chunk_prefix,
                                                              const uint32_t* __restrict__ bsum, uint32_t blk) {
@@ -147,9 +130,13 @@ __device__ __forceinline__ void scan_apply_block(const SortSet* __restrict__ set
     lflat[e] = v;
   }
   __syncthreads();
+  uint32_t part = 0;
+  for (uint32_t q = chunk_prefix[s] + threadIdx.x; q < b; q += kScanThreads) part += bsum[q];
+  uint32_t base;
+  block_exclusive_scan(part, lw, base);
   const uint4 v = lc[threadIdx.x];
   uint32_t tot;
-  const uint32_t ex = block_exclusive_scan(v.x + v.y + v.z + v.w, lw, tot) + bsum[b];
+  const uint32_t ex = block_exclusive_scan(v.x + v.y + v.z + v.w, lw, tot) + base;
   lc[threadIdx.x] = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
   __syncthreads();
 #pragma unroll
@@ -158,7 +145,7 @@ __device__ __forceinline__ void scan_apply_block(const SortSet* __restrict__ set
     const uint32_t c = c0 + e;
     if (c < nc) S.off[c] = lflat[e];
   }
-  if (b + 1 == chunk_prefix[s + 1] && threadIdx.x == 0) S.off[nc] = bsum[b] + tot;
+  if (b + 1 == chunk_prefix[s + 1] && threadIdx.x == 0) S.off[nc] = base + tot;
 }
 
 __device__ __forceinline__ void scatter_block(const SortSet* __restrict__ sets, int nsets,
