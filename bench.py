@@ -126,6 +126,32 @@ def cpu_baseline(sc, budget_s: float):
     }
 
 
+def scale_leg(sph, scenes, torch, args):
+    """16,777,216 particles in two unequal blocks, 2^24 cells, 65,536 agents in flocks."""
+    sc = scenes.config2()
+    log(f"[bench] scale: n={sc.n} agents={sc.n_agents}")
+    stream = torch.cuda.current_stream().cuda_stream
+    sim = sph.create(sc, stream=stream)
+    K = args.scale_steps
+    sim.step_profiled(25)
+    torch.cuda.synchronize()
+    pairs0 = int(sim.read(sph.PAIR_COUNT)[0])
+    t0 = time.perf_counter()
+    ph = sim.step_profiled(K)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = int(sim.read(sph.PAIR_COUNT)[0]) - pairs0
+    info = sim.info()
+    sim.close()
+    b_alg = 154.0 + 24.0 * info["cells"] / sc.n
+    ms = 1e3 * wall / K
+    return {"workload": "two blocks 128x256x384 + 128x256x128 = 16,777,216 particles + 65,536 boids, h=0.01, "
+                        "dt=1e-4, 2^24 cells", "steps": K, "ms_per_step": ms,
+            "particle_steps_per_s": sc.n * K / wall, "pair_interactions_per_s": pairs / wall,
+            "mean_neighbours": pairs / (K * sc.n), "step_hbm_frac": b_alg * sc.n / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+            "kernel_us_per_step": {k: 1e3 * v / K for k, v in ph.items()}}
+
+
 def batched_leg(sph, scenes, torch, args):
     """512 independent dam breaks of uneven size: one batched context vs a loop of plain steps."""
     scs = scenes.batched(args.scenes)
@@ -204,10 +230,13 @@ def closure_leg(sph, scenes, torch, args):
     sc = scenes.config4()
     K = args.closure_steps
     res = {"pairs": got, "collect_s": t_collect, "train": rep, "steps": K}
-    for name, attach in (("exact", False), ("closure", True)):
+    # exact gather; the closure under its controller (2 % bound, check every
+    # 50 steps); the closure with an unbounded threshold, which times the
+    # surrogate path whatever its error
+    for name, attach, bound in (("exact", False, 0.0), ("closure", True, 0.02), ("surrogate_forced", True, 1e30)):
         sim = sph.create(sc, stream=stream)
         if attach:
-            sim.attach_closure(cl, check_every=50, max_rel_rms=0.02)
+            sim.attach_closure(cl, check_every=50, max_rel_rms=bound)
         ph = sim.step_profiled(K)
         res[name] = {"agents_us_per_step": 1e3 * ph["agents"] / K, "ms_per_step": sum(ph.values()) / K}
         if attach:
@@ -215,6 +244,8 @@ def closure_leg(sph, scenes, torch, args):
             sim.attach_closure(None)
         sim.close()
     res["coupling_speedup"] = res["exact"]["agents_us_per_step"] / res["closure"]["agents_us_per_step"]
+    res["coupling_speedup_surrogate_path"] = (res["exact"]["agents_us_per_step"] /
+                                              res["surrogate_forced"]["agents_us_per_step"])
     cl.close()
     return res
 
@@ -228,6 +259,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--scale", action="store_true", help="add the 16.7M-particle scale workload")
+    ap.add_argument("--scale-steps", type=int, default=200)
     ap.add_argument("--batched", action="store_true", help="add the batched-scenes comparison")
     ap.add_argument("--scenes", type=int, default=512)
     ap.add_argument("--batched-steps", type=int, default=100)
@@ -367,6 +400,8 @@ def main():
         "kernel_us_per_step": {k: 1e3 * vms / K for k, vms in phase_ms.items()},
         "graph_ms_per_step": graph_ms,
     }
+    if args.scale:
+        result["scale"] = scale_leg(sph, scenes, torch, args)
     if args.batched:
         result["batched"] = batched_leg(sph, scenes, torch, args)
     if args.closure:

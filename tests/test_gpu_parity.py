@@ -110,6 +110,27 @@ def test_config1_full_size_sampled_graph():
     sim.close()
 
 
+def test_config2_full_size_sampled():
+    """16,777,216 particles in two blocks of unequal height on a 2^24-cell grid,
+    65,536 agents in flocks: integer outputs on every element, floats on a sample."""
+    sc = scenes.config2()
+    print("[parity] config2 full size", flush=True)
+    sim = sph.create(sc, flags=sph.FLAG_DIAGNOSTICS)
+    sim.step(1)
+    x, v, y, u = state(sim)
+    sim.step(1)
+    g = gpu_fields(sim)
+    rng = np.random.default_rng(12)
+    fs = np.unique(np.concatenate([rng.choice(sc.n, 1000, replace=False), np.arange(32),
+                                   np.arange(sc.n - 32, sc.n)]))
+    as_ = np.unique(rng.choice(sc.n_agents, 256, replace=False))
+    ref = oracle.step(sc.params, x, v, y, u, fsample=fs, asample=as_, nbr_mode=1)
+    rep = {}
+    compare_step(g, ref, sc.params, fs=fs, as_=as_, report=rep)
+    print("[parity] config2 errors:", {k: f"{v:.2e}" for k, v in rep.items()}, flush=True)
+    sim.close()
+
+
 def test_graph_replay_equals_eager():
     sc = scenes.config0c()
     a = sph.create(sc)
