@@ -7,13 +7,16 @@ dt = 2e-4 -- seeded synthetic inputs, already resident in HBM when timing
 starts.  A step is one pass of the whole path: cell keys + counting sort,
 density, boid steering + coupling, forces + integration.
 
-Two regions run the same K steps from the same initial state:
-  * timed region: K steps launched directly on the library's stream; the
-    density and force kernels carry HIP events recorded at their own start
-    and end, every other phase HIP events between launches (per-kernel
-    durations and the whole-step time; `value` comes from this region);
-  * graph region: K steps replayed from captured HIP graphs, without the
-    events (reported beside).
+Three regions run the same K steps from the same initial state:
+  * timed region: K steps launched directly on the library's stream, with
+    HIP events only at the density and force kernels' own start and end (the
+    whole-step time, `value`, and the dominant kernel's duration for the
+    roofline come from this region);
+  * phase region: the same K steps with an event between every two phases
+    as well (the per-phase breakdown; the extra events cost some time
+    between launches, so its step time is reported but not used);
+  * graph region: K steps replayed from captured HIP graphs, without events
+    (reported beside).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -49,10 +52,10 @@ FLOP_FORCE_PER_PARTICLE = 30
 
 # HBM traffic of one force + integration launch from two rocprofv3 counter
 # runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scale factors a plain
-# 1 GiB device copy reads on the same counters; first 20 steps of this
-# workload), valid only for the kernel sources it was measured on.
-TRAFFIC_FORCE = {"sources_sha256_16": "b81040d89a62bc34", "bytes_per_launch": 341.3e6,
-                 "measured_on": "first 20 steps"}
+# 1 GiB device copy reads on the same counters), averaged over the 1,000 steps
+# this script times; valid only for the kernel sources it was measured on.
+TRAFFIC_FORCE = {"sources_sha256_16": "249306abc64daf17", "bytes_per_launch": 324.3e6,
+                 "measured_on": "the 1,000 timed steps"}
 FORCE_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
 
 
@@ -133,11 +136,11 @@ def scale_leg(sph, scenes, torch, args):
     stream = torch.cuda.current_stream().cuda_stream
     sim = sph.create(sc, stream=stream)
     K = args.scale_steps
-    sim.step_profiled(25)
+    sim.step_timed(25)
     torch.cuda.synchronize()
     pairs0 = int(sim.read(sph.PAIR_COUNT)[0])
     t0 = time.perf_counter()
-    ph = sim.step_profiled(K)
+    ph = sim.step_timed(K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = int(sim.read(sph.PAIR_COUNT)[0]) - pairs0
@@ -268,7 +271,6 @@ def main():
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--closure-steps", type=int, default=1000)
-    ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the HBM "
                          "byte counters of a profiler against a kernel of known traffic) and exit")
@@ -321,22 +323,33 @@ def main():
     def make():
         return sph.Simulation(sc.params, *inputs, stream=stream)
 
-    # ---- timed region: K steps, HIP events after every kernel ----
+    # ---- timed region: K steps, HIP events at the density and force kernels ----
     sim = make()
     info = sim.info()
-    sim.step_profiled(W)
+    sim.step_timed(W)
     torch.cuda.synchronize()
     pairs0 = int(sim.read(sph.PAIR_COUNT)[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    phase_ms = sim.step_profiled(K)
+    kernel_ms = sim.step_timed(K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = int(sim.read(sph.PAIR_COUNT)[0]) - pairs0
     sim.close()
-    gpu_ms = sum(phase_ms.values())
     ms_per_step = 1e3 * wall / K
-    log(f"[bench] timed region: {ms_per_step:.4f} ms/step wall, {gpu_ms / K:.4f} ms/step in kernels")
+    log(f"[bench] timed region: {ms_per_step:.4f} ms/step wall; density {1e3 * kernel_ms['density'] / K:.2f} us, "
+        f"force_integrate {1e3 * kernel_ms['force_integrate'] / K:.2f} us per step")
+
+    # ---- phase region: same K steps, an event between every two phases ----
+    sim = make()
+    sim.step_profiled(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phase_ms = sim.step_profiled(K)
+    torch.cuda.synchronize()
+    phase_wall_ms = 1e3 * (time.perf_counter() - t0) / K
+    sim.close()
+    log(f"[bench] phase region: {phase_wall_ms:.4f} ms/step wall, {sum(phase_ms.values()) / K:.4f} ms/step in phases")
     for k, vms in phase_ms.items():
         log(f"[bench]   {k:16s} {1e3 * vms / K:9.2f} us/step")
 
@@ -369,7 +382,7 @@ def main():
     # roofline of the dominant kernel (force + integration): bound by vector
     # ALU issue, not HBM (about 25 FP32 operations per byte it must move)
     dom = "force_integrate"
-    t_dom = phase_ms[dom] / K * 1e-3
+    t_dom = kernel_ms[dom] / K * 1e-3
     flop = (FLOP_FORCE_PER_PAIR * pairs / K + FLOP_FORCE_PER_PARTICLE * n)
     ach = flop / t_dom / 1e12
     ach_hbm = kernel_bytes(dom, n, cells, agents) / t_dom / 1e9
@@ -397,7 +410,9 @@ def main():
         "b_alg_bytes_per_particle_step": b_alg,
         "pair_interactions_per_s": pairs / wall,
         "mean_neighbours": pairs / (K * n),
-        "kernel_us_per_step": {k: 1e3 * vms / K for k, vms in phase_ms.items()},
+        "kernel_us_per_step": {k: 1e3 * vms / K for k, vms in kernel_ms.items()},
+        "phase_region": {"ms_per_step": phase_wall_ms,
+                         "us_per_step": {k: 1e3 * vms / K for k, vms in phase_ms.items()}},
         "graph_ms_per_step": graph_ms,
     }
     if args.scale:

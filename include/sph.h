@@ -248,6 +248,13 @@ sph_status sph_closure_stats_get(sph_ctx* ctx, sph_closure_stats* out);
    SPH_STEP_PHASES; sph_phase_name(p) names phase p. */
 #define SPH_STEP_PHASES 9
 sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases);
+/* Timing with the least disturbance: run n_steps steps launched directly,
+   with HIP events only at the density and force kernels' own start and end
+   (no event between phases, so the phases follow each other as in
+   sph_step).  kernel_ms[0] receives the summed density time and kernel_ms[1]
+   the summed force + integration time, in milliseconds (both 0 when the
+   context has no fluid).  kernel_ms is a host array of 2 doubles. */
+sph_status sph_step_timed(sph_ctx* ctx, int32_t n_steps, double* kernel_ms);
 const char* sph_phase_name(int32_t phase);
 
 void sph_destroy(sph_ctx* ctx);

@@ -99,7 +99,7 @@ class Info(ctypes.Structure):
 
 
 EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_bytes", "sph_info_get",
-           "sph_capture", "sph_step_profiled", "sph_phase_name", "sph_autotune", "sph_tuning_set",
+           "sph_capture", "sph_step_profiled", "sph_step_timed", "sph_phase_name", "sph_autotune", "sph_tuning_set",
            "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_destroy", "sph_last_error",
            "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
            "sph_closure_adam_step", "sph_closure_weights", "sph_closure_destroy", "sph_closure_last_error",
@@ -138,6 +138,8 @@ def lib() -> ctypes.CDLL:
         L.sph_capture.argtypes = [vp, i32]
         L.sph_step_profiled.restype = ctypes.c_int
         L.sph_step_profiled.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i32]
+        L.sph_step_timed.restype = ctypes.c_int
+        L.sph_step_timed.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
         L.sph_phase_name.restype = ctypes.c_char_p
         L.sph_phase_name.argtypes = [i32]
         L.sph_autotune.restype = ctypes.c_int
@@ -275,6 +277,13 @@ class Simulation:
         buf = (ctypes.c_double * STEP_PHASES)()
         _check(lib().sph_step_profiled(self._ctx, int(n), buf, STEP_PHASES), self._ctx)
         return {lib().sph_phase_name(p).decode(): buf[p] for p in range(STEP_PHASES)}
+
+    def step_timed(self, n: int) -> Dict[str, float]:
+        """Run n directly launched steps with events only at the density and force kernels'
+        start and end; summed ms of those two kernels."""
+        buf = (ctypes.c_double * 2)()
+        _check(lib().sph_step_timed(self._ctx, int(n), buf), self._ctx)
+        return {"density": buf[0], "force_integrate": buf[1]}
 
     def autotune(self, steps_per_trial: int = 5) -> Dict:
         """Time every execution form on this state (restored afterwards); keep the fastest."""

@@ -496,19 +496,29 @@ sph_status set_tiling(sph_ctx* ctx, int tx, int variant) {
 sph_status sph_ctx_closure_buffers(sph_ctx* ctx) {
   if (ctx->cl_arena) return SPH_OK;
   const size_t A = std::max<uint32_t>(ctx->A, 1);
-  const size_t sz[] = {2 * A * kFeat, 12 * A, 4 * A, 8 * A, 4 * kClWords, 4};
+  const uint32_t noff = ctx->C + (uint32_t)ctx->nscenes;
+  const size_t sz[] = {2 * A * kFeat, 12 * A, 4 * A, 8 * A, 4 * kClWords, 4, 12 * (size_t)noff,
+                       4 * ((size_t)ctx->nscenes + 1)};
+  constexpr int kBufs = (int)(sizeof sz / sizeof sz[0]);
   size_t tot = 0;
   for (size_t b : sz) tot += align_up(b, 256);
   hipError_t e = hipMalloc((void**)&ctx->cl_arena, tot);
   if (e != hipSuccess) return fail(ctx, SPH_ENOMEM, "closure buffers: %s", hipGetErrorString(e));
   char* p = ctx->cl_arena;
-  void** dst[] = {(void**)&ctx->cplan.feat, (void**)&ctx->cplan.fhat, (void**)&ctx->cplan.occ, (void**)&ctx->cplan.err,
-                  (void**)&ctx->cplan.state, (void**)&ctx->cplan.relrms};
-  for (int k = 0; k < 6; ++k) {
+  void** dst[kBufs] = {(void**)&ctx->cplan.feat,  (void**)&ctx->cplan.fhat,   (void**)&ctx->cplan.occ,
+                       (void**)&ctx->cplan.err,   (void**)&ctx->cplan.state,  (void**)&ctx->cplan.relrms,
+                       (void**)&ctx->cplan.cvs,   (void**)&ctx->cplan.oprefix};
+  for (int k = 0; k < kBufs; ++k) {
     *dst[k] = p;
     p += align_up(sz[k], 256);
   }
+  ctx->cplan.noff = noff;
+  std::vector<uint32_t> opre((size_t)ctx->nscenes + 1);
+  for (int s = 0; s < ctx->nscenes; ++s) opre[s] = ctx->hs[s].obase;
+  opre[ctx->nscenes] = noff;
   e = hipMemsetAsync(ctx->cl_arena, 0, tot, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->cplan.oprefix, opre.data(), 4 * opre.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(ctx, SPH_EHIP, "closure buffers: %s", hipGetErrorString(e));
   return SPH_OK;
@@ -558,47 +568,53 @@ static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start =
 // events recorded on the stream between launches).
 static bool kernel_timed(int p) { return p == kSortPhases + 1 || p == kSortPhases + 3; }
 
-constexpr int kProfChunk = 25;                          // steps per set of events
-constexpr int kProfEvents = kStepPhases + 1 + 2 * 2;    // per step: markers, two start/stop pairs
+constexpr int kProfChunk = 25;  // steps per set of events
+constexpr int kKernelEvents = 4; // per step: start / stop of the density and force kernels
 
-// Enqueue n steps with a marker event before the first phase and after every
-// phase, and start / stop events around the density and force kernels.
-static hipError_t enqueue_timed(sph_ctx* ctx, int n, const hipEvent_t* ev, hipStream_t st) {
+// Events per step: with markers, one before the first phase and one after
+// every phase, then the kernel start / stop pairs.
+static int step_events(bool markers) { return (markers ? kStepPhases + 1 : 0) + kKernelEvents; }
+
+// Enqueue n directly launched steps with their events.
+static hipError_t enqueue_timed(sph_ctx* ctx, int n, const hipEvent_t* ev, bool markers, hipStream_t st) {
   hipError_t he = hipSuccess;
+  const int ne = step_events(markers), k0 = markers ? kStepPhases + 1 : 0;
   for (int s = 0; s < n && he == hipSuccess; ++s) {
-    const hipEvent_t* e = ev + (size_t)s * kProfEvents;
-    he = hipEventRecord(e[0], st);
+    const hipEvent_t* e = ev + (size_t)s * ne;
+    if (markers) he = hipEventRecord(e[0], st);
     int pair = 0;
     for (int p = 0; p < kStepPhases && he == hipSuccess; ++p) {
       if (kernel_timed(p)) {
-        launch_phase(ctx, p, st, e[kStepPhases + 1 + 2 * pair], e[kStepPhases + 2 + 2 * pair]);
+        launch_phase(ctx, p, st, e[k0 + 2 * pair], e[k0 + 1 + 2 * pair]);
         ++pair;
       } else {
         launch_phase(ctx, p, st);
       }
-      he = hipEventRecord(e[p + 1], st);
+      if (markers) he = hipEventRecord(e[p + 1], st);
     }
   }
   if (he == hipSuccess) he = hipGetLastError();
   return he;
 }
 
-static sph_status add_elapsed(sph_ctx* ctx, int n, const hipEvent_t* ev, double* phase_ms) {
+// Adds the durations of n steps: per phase (markers) or of the two kernels.
+static sph_status add_elapsed(sph_ctx* ctx, int n, const hipEvent_t* ev, bool markers, double* out) {
+  const int ne = step_events(markers), k0 = markers ? kStepPhases + 1 : 0;
   for (int s = 0; s < n; ++s) {
-    const hipEvent_t* e = ev + (size_t)s * kProfEvents;
+    const hipEvent_t* e = ev + (size_t)s * ne;
     int pair = 0;
     for (int p = 0; p < kStepPhases; ++p) {
       float ms = 0.0f;
-      hipError_t he;
+      hipError_t he = hipSuccess;
       if (kernel_timed(p)) {
-        he = ctx->phys.nf ? hipEventElapsedTime(&ms, e[kStepPhases + 1 + 2 * pair], e[kStepPhases + 2 + 2 * pair])
-                          : hipSuccess;
+        if (ctx->phys.nf) he = hipEventElapsedTime(&ms, e[k0 + 2 * pair], e[k0 + 1 + 2 * pair]);
+        if (he == hipSuccess) out[markers ? p : pair] += ms;
         ++pair;
-      } else {
+      } else if (markers) {
         he = hipEventElapsedTime(&ms, e[p], e[p + 1]);
+        if (he == hipSuccess) out[p] += ms;
       }
       if (he != hipSuccess) return fail(ctx, SPH_EHIP, "hipEventElapsedTime: %s", hipGetErrorString(he));
-      phase_ms[p] += ms;
     }
   }
   return SPH_OK;
@@ -606,12 +622,13 @@ static sph_status add_elapsed(sph_ctx* ctx, int n, const hipEvent_t* ev, double*
 
 // Steps are launched directly, kProfChunk at a time; two sets of events
 // alternate so the next chunk is queued before the previous one is read back.
-sph_status sph_profile_impl(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases) {
-  if (n_phases < kStepPhases) return fail(ctx, SPH_EINVAL, "phase_ms must hold %d entries", kStepPhases);
-  for (int p = 0; p < n_phases; ++p) phase_ms[p] = 0.0;
+// markers: out[p] per phase (kStepPhases entries); else out[0] density and
+// out[1] force kernel time only.
+static sph_status sph_profile_impl(sph_ctx* ctx, int32_t n_steps, double* out, bool markers) {
   if (n_steps <= 0) return SPH_OK;
   hipStream_t st = ctx->stream;
-  const size_t ne = (size_t)kProfChunk * kProfEvents;
+  const int nes = step_events(markers);
+  const size_t ne = (size_t)kProfChunk * nes;
   while (ctx->prof_ev.size() < 2 * ne) {
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return fail(ctx, SPH_EHIP, "hipEventCreate failed");
@@ -623,14 +640,15 @@ sph_status sph_profile_impl(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int
     if (done < n_steps) {
       cur = pending == 0 ? 1 : 0;
       n = std::min<int32_t>(kProfChunk, n_steps - done);
-      hipError_t he = enqueue_timed(ctx, n, ctx->prof_ev.data() + cur * ne, st);
+      hipError_t he = enqueue_timed(ctx, n, ctx->prof_ev.data() + cur * ne, markers, st);
       if (he != hipSuccess) return fail(ctx, SPH_EHIP, "profiled step: %s", hipGetErrorString(he));
       done += n;
     }
     if (pending >= 0) {
       const hipEvent_t* ev = ctx->prof_ev.data() + pending * ne;
-      HIPCHK(hipEventSynchronize(ev[(size_t)(pending_n - 1) * kProfEvents + kStepPhases]));
-      sph_status s = add_elapsed(ctx, pending_n, ev, phase_ms);
+      // the last event of the chunk: the final marker, or the last force stop
+      HIPCHK(hipEventSynchronize(ev[(size_t)pending_n * nes - 1]));
+      sph_status s = add_elapsed(ctx, pending_n, ev, markers, out);
       if (s != SPH_OK) return s;
       ctx->steps += pending_n;
     }
@@ -1116,7 +1134,16 @@ sph_status sph_capture(sph_ctx* ctx, int32_t n_steps) {
 sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases) {
   if (!ctx || !phase_ms) return fail(ctx, SPH_EINVAL, "NULL argument");
   if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
-  return sph_profile_impl(ctx, n_steps, phase_ms, n_phases);
+  if (n_phases < kStepPhases) return fail(ctx, SPH_EINVAL, "phase_ms must hold %d entries", kStepPhases);
+  for (int p = 0; p < n_phases; ++p) phase_ms[p] = 0.0;
+  return sph_profile_impl(ctx, n_steps, phase_ms, true);
+}
+
+sph_status sph_step_timed(sph_ctx* ctx, int32_t n_steps, double* kernel_ms) {
+  if (!ctx || !kernel_ms) return fail(ctx, SPH_EINVAL, "NULL argument");
+  if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
+  kernel_ms[0] = kernel_ms[1] = 0.0;
+  return sph_profile_impl(ctx, n_steps, kernel_ms, false);
 }
 
 const char* sph_phase_name(int32_t phase) {

@@ -102,6 +102,48 @@ __device__ __forceinline__ int find_set(const uint32_t* __restrict__ prefix, int
   return lo;
 }
 
+// Values the compiler cannot prove wave-uniform but that are: kept in scalar registers.
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// Row spans of a stencil (up to 64 rows, lane r holding row r) as a flat list:
+// pre[r] = first flat index of row r (pre[nrows] = total), dlt[r] = start_r - pre[r].
+struct FlatRows {
+  uint32_t* pre;
+  uint32_t* dlt;
+  uint32_t total;
+};
+
+__device__ __forceinline__ FlatRows flat_rows(uint32_t* pre, uint32_t* dlt, int lane, int nrows, uint32_t start,
+                                              uint32_t len) {
+  __builtin_amdgcn_wave_barrier();  // earlier reads of pre / dlt by this wave come first
+  uint32_t incl = lane < nrows ? len : 0u;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)incl, d);
+    if (lane >= d) incl += o;
+  }
+  const uint32_t excl = incl - (lane < nrows ? len : 0u);
+  if (lane < nrows) {
+    pre[lane] = excl;
+    dlt[lane] = start - excl;
+  }
+  const uint32_t total = uniform_u32((uint32_t)__shfl((int)incl, kWave - 1));
+  if (lane == 0) pre[nrows] = total;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return FlatRows{pre, dlt, total};
+}
+
+// Element index of flat position t (< total), advancing the lane's row cursor r.
+__device__ __forceinline__ uint32_t flat_index(const FlatRows& F, uint32_t t, int& r) {
+  while (t >= F.pre[r + 1]) ++r;
+  return F.dlt[r] + t;
+}
+
 // Reflecting walls: a coordinate that left [lo, hi] is mirrored back and its
 // velocity component scaled by -e; finally the coordinate is clamped.
 __device__ __forceinline__ void wall(float& x, float& v, float lo, float hi, float e) {

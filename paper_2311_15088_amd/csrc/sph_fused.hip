@@ -18,6 +18,7 @@
 // every later barrier and every later launch sees the flag and leaves at once,
 // so the grid always drains.
 #include "sph_api_internal.hpp"
+#include "sph_agents_impl.hpp"
 #include "sph_fluid_impl.hpp"
 #include "sph_sort_impl.hpp"
 

@@ -56,21 +56,29 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, const uint32_t* gate) 
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
   const int sr = tid >> 2, sk = (tid & 3) * 8;  // staging: row / column sr, k offset sk
+  // A rows with contiguous k and 16-byte aligned rows are staged 8 elements at a time
+  const bool a_vec = g.sak == 1 && (g.sam & 7) == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
   for (int k0 = 0; k0 < g.K; k0 += kGK) {
     uint16_t av[8], bv[8];
+    uint4 a4 = make_uint4(0, 0, 0, 0);
     const int m = m0 + sr, n = n0 + sr;
+    const bool a_full = a_vec && m < g.M && k0 + sk + 8 <= g.K;
+    if (a_full) a4 = *reinterpret_cast<const uint4*>(g.A + (long long)m * g.sam + k0 + sk);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = k0 + sk + q;
-      av[q] = (m < g.M && k < g.K) ? g.A[(long long)m * g.sam + (long long)k * g.sak] : (uint16_t)0;
+      if (!a_full) av[q] = (m < g.M && k < g.K) ? g.A[(long long)m * g.sam + (long long)k * g.sak] : (uint16_t)0;
       bv[q] = (n < g.N && k < g.K) ? g.B[(long long)k * g.sbk + (long long)n * g.sbn] : (uint16_t)0;
     }
     __syncthreads();
+    if (a_full) {
+      *reinterpret_cast<uint4*>(&As[sr][sk]) = a4;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[sr][sk + q] = av[q];
-      Bs[sr][sk + q] = bv[q];
+      for (int q = 0; q < 8; ++q) As[sr][sk + q] = av[q];
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Bs[sr][sk + q] = bv[q];
     __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 #pragma unroll
@@ -141,16 +149,17 @@ static GemmArgs gargs(int M, int N, int K, const uint16_t* A, long long sam, lon
 
 // ---------------------------------------------------------------- forward --
 
+// keep_z: store the pre-activations Z1, Z2 (needed by a backward pass only)
 static void forward_gated(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, const uint32_t* gate,
-                          hipStream_t st) {
+                          bool keep_z, hipStream_t st) {
   // Z1 = X W1 + b1, H1 = bf16(gelu(Z1))
   GemmArgs g = gargs(rows, kHid, kFeat, x, kFeat, 1, W.wb + kOffW1, kHid, 1);
-  g.Z = wk.z1;
+  g.Z = keep_z ? wk.z1 : nullptr;
   g.Cb = wk.h1;
   g.bias = W.w + kOffB1;
   gemm(g, kEpiBiasGelu, gate, st);
   g = gargs(rows, kHid, kHid, wk.h1, kHid, 1, W.wb + kOffW2, kHid, 1);
-  g.Z = wk.z2;
+  g.Z = keep_z ? wk.z2 : nullptr;
   g.Cb = wk.h2;
   g.bias = W.w + kOffB2;
   gemm(g, kEpiBiasGelu, gate, st);
@@ -161,7 +170,7 @@ static void forward_gated(const MlpWeights& W, const uint16_t* x, int rows, MlpW
 }
 
 void mlp_forward(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, hipStream_t st) {
-  forward_gated(W, x, rows, wk, nullptr, st);
+  forward_gated(W, x, rows, wk, nullptr, true, st);
 }
 
 // --------------------------------------------------------------- backward --
@@ -295,17 +304,58 @@ void mlp_refresh_bf16(const MlpWeights& W, hipStream_t st) {
 
 // ---------------------------------------------------------------- features --
 
-// One wavefront per agent; lane q is cell q of the agent's 4 x 4 x 4 block
-// (x fastest): count / 8 and (mean fluid velocity - agent velocity) / 0.5.
+// Velocity sum of every fluid cell, summed in cell order (one thread per
+// cell-offset entry; a scene's last entry bounds its last cell).
+__global__ void __launch_bounds__(256) k_cell_vsum(PhysPlan P, ClosurePlan C, int always) {
+  if (!always && !C.state[kClNeed]) return;
+  const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= C.noff) return;
+  const int s = find_set(C.oprefix, P.nscenes, g);
+  const DScene& S = P.scenes[s];
+  if (g - S.obase >= S.g.ncells) return;
+  const uint32_t j0 = P.off[g], j1 = P.off[g + 1];
+  float vs[3] = {0.0f, 0.0f, 0.0f};
+  uint32_t t = j0;
+  for (; t + 4 <= j1; t += 4) {  // four particles' loads in flight; the sums stay in cell order
+    const uint32_t j = S.pbase + t;
+    float w[3][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      w[0][u] = P.svx[j + u];
+      w[1][u] = P.svy[j + u];
+      w[2][u] = P.svz[j + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vs[0] += w[0][u];
+      vs[1] += w[1][u];
+      vs[2] += w[2][u];
+    }
+  }
+  for (; t < j1; ++t) {
+    const uint32_t j = S.pbase + t;
+    vs[0] += P.svx[j];
+    vs[1] += P.svy[j];
+    vs[2] += P.svz[j];
+  }
+  C.cvs[g] = vs[0];
+  C.cvs[C.noff + g] = vs[1];
+  C.cvs[2 * (size_t)C.noff + g] = vs[2];
+}
+
+// One wavefront per agent, agents taken in cell order; lane q is cell q of
+// the agent's 4 x 4 x 4 block (x fastest): count / 8 and (mean fluid velocity
+// - agent velocity) / 0.5, from the cell offsets and the cell velocity sums.
 template <int BD>
 __global__ void __launch_bounds__(BD) k_features(PhysPlan P, ClosurePlan C, int always) {
   if (!always && !C.state[kClNeed]) return;
   const uint32_t gi = (blockIdx.x * BD + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (gi >= P.na) return;
-  const int s = find_set(P.aprefix, P.nscenes, gi);
+  const int s = (int)uniform_u32((uint32_t)find_set(P.aprefix, P.nscenes, gi));
   const DScene& S = P.scenes[s];
-  const uint32_t a = S.abase + (gi - P.aprefix[s]);
+  // row a of the features is agent a
+  const uint32_t a = S.abase + uniform_u32(P.asid[S.abase + (gi - P.aprefix[s])]);
   const float ya[3] = {P.agx[a], P.agy[a], P.agz[a]};
   const float ua[3] = {P.aux[a], P.auy[a], P.auz[a]};
   const int l[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
@@ -322,16 +372,11 @@ __global__ void __launch_bounds__(BD) k_features(PhysPlan P, ClosurePlan C, int 
   uint32_t n = 0;
   float vs[3] = {0.0f, 0.0f, 0.0f};
   if (inside) {
-    const uint32_t* off = P.off + S.obase;
-    const uint32_t key = hash3(S.g, c[0], c[1], c[2]);
-    const uint32_t j0 = off[key], j1 = off[key + 1];
-    n = j1 - j0;
-    for (uint32_t t = j0; t < j1; ++t) {
-      const uint32_t j = S.pbase + t;
-      vs[0] += P.svx[j];
-      vs[1] += P.svy[j];
-      vs[2] += P.svz[j];
-    }
+    const uint32_t g = S.obase + hash3(S.g, c[0], c[1], c[2]);
+    n = P.off[g + 1] - P.off[g];
+    vs[0] = C.cvs[g];
+    vs[1] = C.cvs[C.noff + g];
+    vs[2] = C.cvs[2 * (size_t)C.noff + g];
   }
   uint16_t f[4];
   f[0] = f2bf((float)n / 8.0f);
@@ -347,6 +392,7 @@ __global__ void __launch_bounds__(BD) k_features(PhysPlan P, ClosurePlan C, int 
 
 void launch_features(const PhysPlan& P, const ClosurePlan& C, bool always, hipStream_t st) {
   if (!P.na) return;
+  if (C.noff) hipLaunchKernelGGL(k_cell_vsum, dim3((C.noff + 255) / 256), dim3(256), 0, st, P, C, always ? 1 : 0);
   hipLaunchKernelGGL(k_features<256>, dim3((P.na + 3) / 4), dim3(256), 0, st, P, C, always ? 1 : 0);
 }
 
@@ -425,7 +471,7 @@ void launch_closure_end(const ClosurePlan& C, uint32_t na, hipStream_t st) {
 
 void mlp_forward_gated(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, const uint32_t* gate,
                        hipStream_t st) {
-  forward_gated(W, x, rows, wk, gate, st);
+  forward_gated(W, x, rows, wk, gate, false, st);
 }
 
 }  // namespace sph

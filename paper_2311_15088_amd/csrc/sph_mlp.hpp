@@ -80,6 +80,9 @@ struct ClosurePlan {
   float* err;         // [na][2] |fhat - F|^2, |F|^2 at check steps
   uint32_t* state;    // kCl* words (sph_internal.hpp)
   float* relrms;      // [1] last check
+  float* cvs;         // [3][noff] velocity sum of every fluid cell, indexed like the cell offsets
+  uint32_t* oprefix;  // [nscenes + 1] first cell-offset entry of every scene (last = noff)
+  uint32_t noff;      // cell-offset entries of all scenes (cells + one per scene)
   int check_every;
   float max_rel_rms;
 };

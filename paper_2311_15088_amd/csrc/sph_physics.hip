@@ -2,6 +2,7 @@
 // launch configurations; the bodies are in sph_fluid_impl.hpp.
 #include <hip/hip_ext.h>
 
+#include "sph_agents_impl.hpp"
 #include "sph_fluid_impl.hpp"
 
 namespace sph {

@@ -148,21 +148,26 @@ def test_graph_replay_equals_eager():
 
 
 def test_profiled_steps_equal_plain_steps():
-    """sph_step_profiled (events read back every 25 steps) advances the state
-    exactly like sph_step."""
+    """sph_step_profiled and sph_step_timed (events read back every 25 steps)
+    advance the state exactly like sph_step."""
     sc = scenes.config0c()
     a = sph.create(sc)
     b = sph.create(sc)
+    c = sph.create(sc)
     for n in (27, 3, 75):  # a chunk and a remainder, a remainder only, three chunks
         a.step(n)
         ph = b.step_profiled(n)
         assert set(ph) == {sph.phase_name(p) for p in range(sph.STEP_PHASES)}
         assert all(v > 0 for v in ph.values())
-        for fa, fb in zip(state(a), state(b)):
+        kt = c.step_timed(n)
+        assert set(kt) == {"density", "force_integrate"} and all(v > 0 for v in kt.values())
+        for fa, fb, fc in zip(state(a), state(b), state(c)):
             np.testing.assert_array_equal(fa, fb)
-    assert a.info()["steps"] == b.info()["steps"] == 105
+            np.testing.assert_array_equal(fa, fc)
+    assert a.info()["steps"] == b.info()["steps"] == c.info()["steps"] == 105
     a.close()
     b.close()
+    c.close()
 
 
 def test_checkpoint_resume_is_bit_identical():
