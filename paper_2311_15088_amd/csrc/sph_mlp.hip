@@ -41,7 +41,8 @@ constexpr int kGT = 64;   // block tile
 constexpr int kGK = 32;   // k step
 constexpr int kGPad = 40; // LDS row length (elements)
 
-template <int EPI>
+// AVEC: A has contiguous k and 16-byte aligned rows, staged 8 elements at a time
+template <int EPI, bool AVEC>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, const uint32_t* gate) {
   if (gate && !*gate) return;
   __shared__ __attribute__((aligned(16))) uint16_t As[kGT][kGPad];
@@ -56,24 +57,35 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, const uint32_t* gate) 
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
   const int sr = tid >> 2, sk = (tid & 3) * 8;  // staging: row / column sr, k offset sk
-  // A rows with contiguous k and 16-byte aligned rows are staged 8 elements at a time
-  const bool a_vec = g.sak == 1 && (g.sam & 7) == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
   for (int k0 = 0; k0 < g.K; k0 += kGK) {
     uint16_t av[8], bv[8];
-    uint4 a4 = make_uint4(0, 0, 0, 0);
     const int m = m0 + sr, n = n0 + sr;
-    const bool a_full = a_vec && m < g.M && k0 + sk + 8 <= g.K;
-    if (a_full) a4 = *reinterpret_cast<const uint4*>(g.A + (long long)m * g.sam + k0 + sk);
+    if constexpr (AVEC) {
+      uint4 a4 = make_uint4(0, 0, 0, 0);
+      if (m < g.M && k0 + sk + 8 <= g.K) {
+        a4 = *reinterpret_cast<const uint4*>(g.A + (long long)m * g.sam + k0 + sk);
+      } else if (m < g.M) {  // the ragged end of k
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = k0 + sk + q;
-      if (!a_full) av[q] = (m < g.M && k < g.K) ? g.A[(long long)m * g.sam + (long long)k * g.sak] : (uint16_t)0;
-      bv[q] = (n < g.N && k < g.K) ? g.B[(long long)k * g.sbk + (long long)n * g.sbn] : (uint16_t)0;
-    }
-    __syncthreads();
-    if (a_full) {
+        for (int q = 0; q < 8; ++q)
+          if (k0 + sk + q < g.K) w[q >> 1] |= (uint32_t)g.A[(long long)m * g.sam + k0 + sk + q] << (16 * (q & 1));
+        a4 = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + sk + q;
+        bv[q] = (n < g.N && k < g.K) ? g.B[(long long)k * g.sbk + (long long)n * g.sbn] : (uint16_t)0;
+      }
+      __syncthreads();
       *reinterpret_cast<uint4*>(&As[sr][sk]) = a4;
     } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + sk + q;
+        av[q] = (m < g.M && k < g.K) ? g.A[(long long)m * g.sam + (long long)k * g.sak] : (uint16_t)0;
+        bv[q] = (n < g.N && k < g.K) ? g.B[(long long)k * g.sbk + (long long)n * g.sbn] : (uint16_t)0;
+      }
+      __syncthreads();
 #pragma unroll
       for (int q = 0; q < 8; ++q) As[sr][sk + q] = av[q];
     }
@@ -119,15 +131,22 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, const uint32_t* gate) 
       }
 }
 
-static void gemm(const GemmArgs& g, int epi, const uint32_t* gate, hipStream_t st) {
-  if (g.M <= 0 || g.N <= 0) return;
+template <bool AVEC>
+static void gemm_v(const GemmArgs& g, int epi, const uint32_t* gate, hipStream_t st) {
   const dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT);
   switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL(k_gemm<kEpiStore>, grid, dim3(256), 0, st, g, gate); break;
-    case kEpiBias: hipLaunchKernelGGL(k_gemm<kEpiBias>, grid, dim3(256), 0, st, g, gate); break;
-    case kEpiBiasGelu: hipLaunchKernelGGL(k_gemm<kEpiBiasGelu>, grid, dim3(256), 0, st, g, gate); break;
-    default: hipLaunchKernelGGL(k_gemm<kEpiGeluBwd>, grid, dim3(256), 0, st, g, gate); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm<kEpiStore, AVEC>), grid, dim3(256), 0, st, g, gate); break;
+    case kEpiBias: hipLaunchKernelGGL((k_gemm<kEpiBias, AVEC>), grid, dim3(256), 0, st, g, gate); break;
+    case kEpiBiasGelu: hipLaunchKernelGGL((k_gemm<kEpiBiasGelu, AVEC>), grid, dim3(256), 0, st, g, gate); break;
+    default: hipLaunchKernelGGL((k_gemm<kEpiGeluBwd, AVEC>), grid, dim3(256), 0, st, g, gate); break;
   }
+}
+
+static void gemm(const GemmArgs& g, int epi, const uint32_t* gate, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return;
+  const bool avec = g.sak == 1 && (g.sam & 7) == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
+  if (avec) gemm_v<true>(g, epi, gate, st);
+  else gemm_v<false>(g, epi, gate, st);
 }
 
 void launch_gemm(const GemmArgs& g, int epilogue, hipStream_t st) { gemm(g, epilogue, nullptr, st); }
