@@ -20,41 +20,48 @@ __global__ void __launch_bounds__(BD) k_agents(PhysPlan P) {
 }
 
 // ----------------------------------------------------------------------------
-// Launch configurations of the fluid passes: (block size, LDS window of the
-// density pass, of the force pass; a halo row longer than the window is
-// staged in pieces).  They are instantiations of the one kernel above; every
-// one produces bit-identical results (the candidate order of each particle
-// does not depend on them).
+// Launch configurations of the fluid passes: block size and LDS window of the
+// density pass, of the force pass (a halo row longer than the window is staged
+// in pieces), and the most own particles per work item.  They are
+// instantiations of the one kernel above; every one produces bit-identical
+// results (the candidate order of each particle does not depend on them).
 struct FluidVariant {
   const void* density;
   const void* force;
-  int bd;
+  int bd_density, bd_force, item_max;
   const char* name;
 };
 
-template <int BD, int CD, int CF>
-static FluidVariant make_variant(const char* name) {
-  return FluidVariant{(const void*)k_fluid<false, BD, CD>, (const void*)k_fluid<true, BD, CF>, BD, name};
+template <int BDD, int CD, int BDF, int CF>
+static FluidVariant make_variant(int item_max, const char* name) {
+  return FluidVariant{(const void*)k_fluid<false, BDD, CD>, (const void*)k_fluid<true, BDF, CF>, BDD, BDF, item_max,
+                      name};
 }
 
 static const FluidVariant* variants() {
+  // the density pass runs fastest with 512-thread blocks and the force pass
+  // (more registers and LDS per thread) with 256; items of at most 256 own
+  // particles suit both
   static const FluidVariant v[] = {
-      make_variant<256, 512, 512>("bd256_win512_512"),
-      make_variant<128, 512, 256>("bd128_win512_256"),
-      make_variant<512, 512, 512>("bd512_win512_512"),
-      make_variant<256, 1024, 1024>("bd256_win1024_1024"),
-      make_variant<256, 256, 256>("bd256_win256_256"),
+      make_variant<512, 512, 256, 512>(256, "d512_f256_win512"),
+      make_variant<256, 512, 256, 512>(256, "bd256_win512_512"),
+      make_variant<128, 512, 128, 256>(128, "bd128_win512_256"),
+      make_variant<512, 512, 512, 512>(512, "bd512_win512_512"),
+      make_variant<256, 1024, 256, 1024>(256, "bd256_win1024_1024"),
+      make_variant<256, 256, 256, 256>(256, "bd256_win256_256"),
+      make_variant<512, 1024, 256, 512>(256, "d512_win1024_f256_win512"),
+      make_variant<1024, 1024, 256, 512>(256, "d1024_win1024_f256_win512"),
   };
   return v;
 }
-constexpr int kNumVariants = 5;
+constexpr int kNumVariants = 8;
 constexpr int kAgentBD = 256;
 
 int fluid_variants() { return kNumVariants; }
 
 int fluid_item_max(int fused, int variant) {
   if (fused) return kFusedBD;
-  return variants()[(variant >= 0 && variant < kNumVariants) ? variant : 0].bd;
+  return variants()[(variant >= 0 && variant < kNumVariants) ? variant : 0].item_max;
 }
 const char* fluid_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? variants()[v].name : nullptr; }
 
@@ -78,12 +85,13 @@ static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st, hipEvent
   const int v = (P.variant >= 0 && P.variant < kNumVariants) ? P.variant : 0;
   const FluidVariant& V = variants()[v];
   const void* fn = force ? V.force : V.density;
+  const int bd = force ? V.bd_force : V.bd_density;
   int& grid = grids[v][force ? 1 : 0];
-  if (!grid) grid = persistent_blocks(fn, V.bd);
+  if (!grid) grid = persistent_blocks(fn, bd);
   const uint32_t g = std::min<uint32_t>((uint32_t)grid, P.ntiles);
   void* args[] = {(void*)&P};
-  if (start || stop) (void)hipExtLaunchKernel(fn, dim3(g), dim3(V.bd), args, 0, st, start, stop, 0);
-  else (void)hipLaunchKernel(fn, dim3(g), dim3(V.bd), args, 0, st);
+  if (start || stop) (void)hipExtLaunchKernel(fn, dim3(g), dim3(bd), args, 0, st, start, stop, 0);
+  else (void)hipLaunchKernel(fn, dim3(g), dim3(bd), args, 0, st);
 }
 
 void launch_tile_list(const PhysPlan& P, hipStream_t st) {
