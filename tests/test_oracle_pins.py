@@ -245,6 +245,11 @@ def test_keys_and_order_match_lexsort():
     np.testing.assert_array_equal(r["key"], key)
     ids = np.arange(sc.n)
     np.testing.assert_array_equal(r["sorted"], np.lexsort((ids, key)))
+    adims, _, ainv, _ = oracle.grid(p, agent=True)
+    ta = (sc.y - np.asarray(p["box_min"], np.float32)).astype(np.float32) * np.float32(ainv)
+    ca = np.clip(np.floor(ta).astype(np.int64), 0, np.asarray(adims) - 1)
+    akey = ca[:, 0] + adims[0] * (ca[:, 1] + adims[1] * ca[:, 2])
+    np.testing.assert_array_equal(r["asorted"], np.lexsort((np.arange(sc.n_agents), akey)))
     np.testing.assert_array_equal(r["cnt"], np.bincount(key, minlength=nc))
     assert r["off"][0] == 0 and r["off"][-1] == sc.n and np.all(np.diff(r["off"].astype(np.int64)) >= 0)
     assert dims == (20, 16, 20)
