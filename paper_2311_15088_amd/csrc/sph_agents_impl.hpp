@@ -36,10 +36,33 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
   const DScene& S = P.scenes[s];
   // waves take the agents in cell order, so that neighbouring waves read
   // neighbouring fluid and agent cells; the agent's own id names its slot
-  const uint32_t la = uniform_u32(P.asid[S.abase + (gi - P.aprefix[s])]);
+  // (its state is read from the cell-ordered copy at the wave's own index,
+  // alongside the id rather than after it)
+  const uint32_t w = S.abase + (gi - P.aprefix[s]);
+  const uint32_t la = uniform_u32(P.asid[w]);
   const uint32_t a = S.abase + la;
-  const float ya[3] = {P.agx[a], P.agy[a], P.agz[a]};
-  const float ua[3] = {P.aux[a], P.auy[a], P.auz[a]};
+  const float ya[3] = {P.asx[w], P.asy[w], P.asz[w]};
+  const float ua[3] = {P.asvx[w], P.asvy[w], P.asvz[w]};
+
+  // bounds of the coupling stencil's first 64 fluid rows (lane q holds row q):
+  // loaded now, together with the boid rows below, and used after them
+  const uint32_t* __restrict__ off = P.off + S.obase;
+  int fx, fy, fz;
+  cell_of(S.g, ya[0], ya[1], ya[2], fx, fy, fz);
+  const int ns = S.ns_c, side = 2 * ns + 1, nrows = side * side;
+  const int fx0 = max(fx - ns, 0), fx1 = min(fx + ns, S.g.dim[0] - 1);
+  auto fluid_row = [&](int q, uint32_t& r0, uint32_t& r1) {
+    r0 = r1 = 0;
+    if (q < nrows) {
+      const int y = fy + q % side - ns, z = fz + q / side - ns;
+      if (y >= 0 && y < S.g.dim[1] && z >= 0 && z < S.g.dim[2]) {
+        r0 = off[hash3(S.g, fx0, y, z)];
+        r1 = off[hash3(S.g, fx1, y, z) + 1];
+      }
+    }
+  };
+  uint32_t rj0_first, rj1_first;
+  fluid_row(lane, rj0_first, rj1_first);
 
   // --- boid rules over the agents in the 27 agent cells ---
   const uint32_t* __restrict__ aoff = P.aoff + S.aobase;
@@ -131,26 +154,15 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
   // A learned closure, when its controller says so, replaces this gather.
   const bool surrogate = P.cl_state && P.cl_state[kClUse];
   const bool check = P.cl_state && P.cl_state[kClCheck];
-  const uint32_t* __restrict__ off = P.off + S.obase;
-  cell_of(S.g, ya[0], ya[1], ya[2], cx, cy, cz);
   float F[3] = {0, 0, 0};
   uint32_t ncpl = 0;
   if (!surrogate) {
     const float rc2 = uniform_f(S.rc2), inv_rc = uniform_f(S.inv_rc), mr0 = uniform_f(S.m_over_rho0);
     const float m = uniform_f(S.m), rho0 = uniform_f(S.rho0), cpk_hc = uniform_f(S.cpk_hc);
     const float cvmu_c = uniform_f(S.cvmu_c);
-    const int ns = S.ns_c, side = 2 * ns + 1, nrows = side * side;
-    const int x0 = max(cx - ns, 0), x1 = min(cx + ns, S.g.dim[0] - 1);
     for (int g0 = 0; g0 < nrows; g0 += kWave) {
-      uint32_t rj0 = 0, rj1 = 0;
-      const int q = g0 + lane;
-      if (q < nrows) {
-        const int y = cy + q % side - ns, z = cz + q / side - ns;
-        if (y >= 0 && y < S.g.dim[1] && z >= 0 && z < S.g.dim[2]) {
-          rj0 = off[hash3(S.g, x0, y, z)];
-          rj1 = off[hash3(S.g, x1, y, z) + 1];
-        }
-      }
+      uint32_t rj0 = rj0_first, rj1 = rj1_first;
+      if (g0) fluid_row(g0 + lane, rj0, rj1);
       const FlatRows R = flat_rows(s_pre[wave], s_dlt[wave], lane, min(kWave, nrows - g0), S.pbase + rj0, rj1 - rj0);
       int cur = 0;
       for (uint32_t t0 = 0; t0 < R.total; t0 += kGatherBatch * kWave) {
