@@ -74,11 +74,12 @@ def force_traffic():
 #   scan_reduce    reads cnt (4)                                       per cell
 #   scan_apply     reads cnt (4), writes off (4), clears cnt (4)       per cell
 #   scatter        reads key, rank, id (12), writes src, id (8)        per particle
-#   fixup_gather   reads src, id, key (12), x, v (24), writes x, v, id (28) per particle
+#   fixup_tile_list reads src, id, key (12), x, v (24), writes x, v, id (28) per particle
+#                  (the work-item list in the same launch: 8 per tile)
 #   density        reads x (12), writes rho, n (8)                     per particle
 #   force_integrate reads x, v, rho (28), writes x', v' (24)           per particle
 #   agents         reads y, u (24), writes y', u' (24)                 per agent
-B_PER_PARTICLE = {"key_count": 20, "scatter": 20, "fixup_gather": 64, "density": 20, "force_integrate": 52}
+B_PER_PARTICLE = {"key_count": 20, "scatter": 20, "fixup_tile_list": 64, "density": 20, "force_integrate": 52}
 B_PER_CELL = {"scan_reduce": 4, "scan_apply": 12}
 
 

@@ -246,7 +246,7 @@ sph_status sph_closure_stats_get(sph_ctx* ctx, sph_closure_stats* out);
    after it, which include the gap between launches.  Events are read back
    every 25 steps while the next 25 run.  n_phases must be >=
    SPH_STEP_PHASES; sph_phase_name(p) names phase p. */
-#define SPH_STEP_PHASES 9
+#define SPH_STEP_PHASES 8
 sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, int32_t n_phases);
 /* Timing with the least disturbance: run n_steps steps launched directly,
    with HIP events only at the density and force kernels' own start and end

@@ -104,7 +104,7 @@ EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_
            "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
            "sph_closure_adam_step", "sph_closure_weights", "sph_closure_destroy", "sph_closure_last_error",
            "sph_closure_attach", "sph_closure_stats_get")
-STEP_PHASES = 9
+STEP_PHASES = 8
 
 _lib = None
 

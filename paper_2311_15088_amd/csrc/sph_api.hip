@@ -535,8 +535,8 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
     for (int32_t k = 0; k < n_steps; ++k) launch_step_fused(F, ctx->fused_variant, st);
   } else {
     for (int32_t k = 0; k < n_steps; ++k) {
-      launch_sort(ctx->sort, st);
-      launch_tile_list(ctx->phys, st);
+      for (int ph = 0; ph < kSortPhases - 1; ++ph) launch_sort_phase(ctx->sort, ph, st);
+      launch_fixup_tiles(ctx->sort, ctx->phys, st);
       launch_density(ctx->phys, st);
       sph_ctx_closure_phase(ctx, st);
       launch_agents(ctx->phys, st);
@@ -552,10 +552,10 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
 // Phase p of one step (p < kStepPhases), in launch order.  start / stop:
 // optional events at the fluid kernels' own start and end.
 static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
-  if (p < kSortPhases) launch_sort_phase(ctx->sort, p, st);
-  else if (p == kSortPhases) launch_tile_list(ctx->phys, st);
-  else if (p == kSortPhases + 1) launch_density(ctx->phys, st, start, stop);
-  else if (p == kSortPhases + 2) {
+  if (p < kSortPhases - 1) launch_sort_phase(ctx->sort, p, st);
+  else if (p == kSortPhases - 1) launch_fixup_tiles(ctx->sort, ctx->phys, st);
+  else if (p == kSortPhases) launch_density(ctx->phys, st, start, stop);
+  else if (p == kSortPhases + 1) {
     sph_ctx_closure_phase(ctx, st);
     launch_agents(ctx->phys, st);
   } else {
@@ -566,7 +566,7 @@ static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start =
 
 // Phases timed by events at their kernel's own start and end (the others by
 // events recorded on the stream between launches).
-static bool kernel_timed(int p) { return p == kSortPhases + 1 || p == kSortPhases + 3; }
+static bool kernel_timed(int p) { return p == kSortPhases || p == kSortPhases + 2; }
 
 constexpr int kProfChunk = 25;  // steps per set of events
 constexpr int kKernelEvents = 4; // per step: start / stop of the density and force kernels
@@ -1147,8 +1147,8 @@ sph_status sph_step_timed(sph_ctx* ctx, int32_t n_steps, double* kernel_ms) {
 }
 
 const char* sph_phase_name(int32_t phase) {
-  static const char* names[kStepPhases] = {"key_count", "scan_reduce", "scan_apply", "scatter", "fixup_gather",
-                                           "tile_list", "density", "agents", "force_integrate"};
+  static const char* names[kStepPhases] = {"key_count", "scan_reduce", "scan_apply",   "scatter",
+                                           "fixup_tile_list", "density", "agents", "force_integrate"};
   return (phase >= 0 && phase < kStepPhases) ? names[phase] : nullptr;
 }
 

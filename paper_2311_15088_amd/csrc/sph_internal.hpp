@@ -73,17 +73,20 @@ struct PhysPlan {
 };
 
 constexpr int kSortPhases = 5;  // key+count, scan reduce, scan apply, scatter, fix-up
+// sort phases 0 .. kSortPhases - 2 (the fix-up is launched with the tile list)
 void launch_sort_phase(const SortPlan& P, int phase, hipStream_t st);
-void launch_sort(const SortPlan& P, hipStream_t st);
 uint32_t scan_chunks(uint32_t ncells);
 
-constexpr int kStepPhases = kSortPhases + 4;  // + tile list, density, agents, force + integration
+// fix-up + work-item list, density, agents, force + integration
+constexpr int kStepPhases = kSortPhases + 3;
 uint32_t fluid_tiles(const DGrid& g, int tx);
 int fluid_variants();
 // particles per work item of the fluid passes: the block size of the form
 int fluid_item_max(int fused, int variant);
 const char* fluid_variant_name(int v);
-void launch_tile_list(const PhysPlan& P, hipStream_t st);
+// The sort's fix-up and the fluid passes' work-item list in one launch (the
+// list needs only the cell offsets, so it overlaps the fix-up).
+void launch_fixup_tiles(const SortPlan& S, const PhysPlan& P, hipStream_t st);
 // start / stop: optional events recorded at the fluid kernel's own start and end
 void launch_density(const PhysPlan& P, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 void launch_agents(const PhysPlan& P, hipStream_t st);

@@ -4,10 +4,21 @@
 
 #include "sph_agents_impl.hpp"
 #include "sph_fluid_impl.hpp"
+#include "sph_sort_impl.hpp"
 
 namespace sph {
 
-__global__ void __launch_bounds__(256) k_tile_list(PhysPlan P) { tile_list_block(P, blockIdx.x); }
+// The sort's fix-up and the work-item list of the fluid passes share one
+// launch.  The list reads only the cell offsets of this step, so it does not
+// wait for the fix-up; its blocks come first in the grid, so that its long
+// per-lane walks over dense tiles start while the fix-up fills the machine.
+static_assert(kSortBD == 256, "one block size for both parts");
+__global__ void __launch_bounds__(256) k_fixup_tiles(const SortSet* __restrict__ sets, int nsets,
+                                                     const uint32_t* __restrict__ bprefix, uint32_t tile_blocks,
+                                                     PhysPlan P) {
+  if (blockIdx.x < tile_blocks) tile_list_block(P, blockIdx.x);
+  else fixup_block(sets, nsets, bprefix, blockIdx.x - tile_blocks);
+}
 
 template <bool FORCE, int BD, int CAP>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
@@ -94,9 +105,10 @@ static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st, hipEvent
   else (void)hipLaunchKernel(fn, dim3(g), dim3(bd), args, 0, st);
 }
 
-void launch_tile_list(const PhysPlan& P, hipStream_t st) {
-  if (!P.nf) return;
-  hipLaunchKernelGGL(k_tile_list, dim3((P.ntiles + 255) / 256), dim3(256), 0, st, P);
+void launch_fixup_tiles(const SortPlan& S, const PhysPlan& P, hipStream_t st) {
+  const uint32_t tb = P.nf ? (P.ntiles + 255) / 256 : 0u;
+  if (tb + S.nblocks)
+    hipLaunchKernelGGL(k_fixup_tiles, dim3(tb + S.nblocks), dim3(256), 0, st, S.sets, S.nsets, S.bprefix, tb, P);
 }
 
 void launch_density(const PhysPlan& P, hipStream_t st, hipEvent_t start, hipEvent_t stop) {

@@ -1,5 +1,6 @@
-// sph_sort.hip -- per-phase kernels of the counting sort; the bodies are in
-// sph_sort_impl.hpp.
+// sph_sort.hip -- per-phase kernels of the counting sort up to the scatter (the
+// fix-up is launched with the work-item list, sph_physics.hip); the bodies are
+// in sph_sort_impl.hpp.
 #include "sph_sort_impl.hpp"
 
 namespace sph {
@@ -22,10 +23,6 @@ __global__ void __launch_bounds__(kSortBD) k_scatter(const SortSet* __restrict__
                                                      const uint32_t* __restrict__ bprefix) {
   scatter_block(sets, nsets, bprefix, blockIdx.x);
 }
-__global__ void __launch_bounds__(kSortBD) k_fixup(const SortSet* __restrict__ sets, int nsets,
-                                                   const uint32_t* __restrict__ bprefix) {
-  fixup_block(sets, nsets, bprefix, blockIdx.x);
-}
 
 void launch_sort_phase(const SortPlan& P, int phase, hipStream_t st) {
   switch (phase) {
@@ -42,14 +39,7 @@ void launch_sort_phase(const SortPlan& P, int phase, hipStream_t st) {
     case 3:
       if (P.nblocks) hipLaunchKernelGGL(k_scatter, dim3(P.nblocks), dim3(kSortBD), 0, st, P.sets, P.nsets, P.bprefix);
       break;
-    case 4:
-      if (P.nblocks) hipLaunchKernelGGL(k_fixup, dim3(P.nblocks), dim3(kSortBD), 0, st, P.sets, P.nsets, P.bprefix);
-      break;
   }
-}
-
-void launch_sort(const SortPlan& P, hipStream_t st) {
-  for (int ph = 0; ph < kSortPhases; ++ph) launch_sort_phase(P, ph, st);
 }
 
 uint32_t scan_chunks(uint32_t ncells) { return (ncells + kChunk - 1) / kChunk; }
