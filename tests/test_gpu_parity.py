@@ -81,6 +81,15 @@ def test_dense_clump_against_oracle():
     assert worst["rho"] < 1e-4
 
 
+def test_wide_coupling_radius():
+    """r_couple = 4h: the coupling stencil has 9 x 9 = 81 fluid rows, more than a
+    wavefront's 64 lanes, so the agents' flattened gather takes two row groups."""
+    sc = scenes.small_dam(nx=12, ny=10, nz=12, n_agents=30, agents="inside")
+    sc.params["r_couple"] = float(np.float32(4 * sc.params["h"]))
+    worst = chained_parity(sc, 2)
+    print(f"[parity] wide coupling worst {worst}", flush=True)
+
+
 def test_paper_literal_kernel_constants():
     sc = scenes.small_dam(nx=10, ny=8, nz=10, n_agents=12)
     sc.params["kernel_norm"] = 1
