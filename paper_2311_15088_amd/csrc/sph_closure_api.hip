@@ -145,7 +145,7 @@ sph_status sph_closure_create(const float* weights, float force_scale, void* hip
   if (!(force_scale > 0.0f)) return cfail(nullptr, SPH_EINVAL, "force_scale must be positive");
   sph_closure* cl = new sph_closure();
   cl->stream = (hipStream_t)hip_stream;
-  const size_t tot = al(4 * kParams) * 5 + al(2 * kParams);
+  const size_t tot = al(4 * kParams) * 5 + al(2 * kParams) + al(2 * (size_t)kWT);
   hipError_t e = hipMalloc((void**)&cl->arena, tot);
   if (e != hipSuccess) {
     delete cl;
@@ -162,6 +162,8 @@ sph_status sph_closure_create(const float* weights, float force_scale, void* hip
   p += al(4 * kParams);
   p += al(4 * kParams);  // spare
   cl->W.wb = (uint16_t*)p;
+  p += al(2 * kParams);
+  cl->W.wt = (uint16_t*)p;
   cl->W.scale = force_scale;
   hipStream_t st = cl->stream;
   e = hipMemsetAsync(cl->arena, 0, tot, st);
@@ -406,8 +408,7 @@ void sph_ctx_closure_phase(sph_ctx* ctx, hipStream_t st) {
     sph_closure* cl = ctx->closure;
     launch_closure_begin(ctx->cplan, st);
     launch_features(ctx->phys, ctx->cplan, false, st);
-    mlp_forward_gated(cl->W, ctx->cplan.feat, (int)ctx->A, cl->wk, ctx->cplan.state + kClNeed, st);
-    launch_closure_apply(ctx->cplan, cl->wk.y, cl->W.scale, ctx->A, st);
+    launch_closure_infer(cl->W, ctx->cplan, ctx->A, st);
   } else if (ctx->features) {
     launch_features(ctx->phys, ctx->cplan, true, st);
   }

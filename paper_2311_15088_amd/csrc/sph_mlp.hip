@@ -168,28 +168,26 @@ static GemmArgs gargs(int M, int N, int K, const uint16_t* A, long long sam, lon
 
 // ---------------------------------------------------------------- forward --
 
-// keep_z: store the pre-activations Z1, Z2 (needed by a backward pass only)
-static void forward_gated(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, const uint32_t* gate,
-                          bool keep_z, hipStream_t st) {
+static void forward(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, hipStream_t st) {
   // Z1 = X W1 + b1, H1 = bf16(gelu(Z1))
   GemmArgs g = gargs(rows, kHid, kFeat, x, kFeat, 1, W.wb + kOffW1, kHid, 1);
-  g.Z = keep_z ? wk.z1 : nullptr;
+  g.Z = wk.z1;
   g.Cb = wk.h1;
   g.bias = W.w + kOffB1;
-  gemm(g, kEpiBiasGelu, gate, st);
+  gemm(g, kEpiBiasGelu, nullptr, st);
   g = gargs(rows, kHid, kHid, wk.h1, kHid, 1, W.wb + kOffW2, kHid, 1);
-  g.Z = keep_z ? wk.z2 : nullptr;
+  g.Z = wk.z2;
   g.Cb = wk.h2;
   g.bias = W.w + kOffB2;
-  gemm(g, kEpiBiasGelu, gate, st);
+  gemm(g, kEpiBiasGelu, nullptr, st);
   g = gargs(rows, kOut, kHid, wk.h2, kHid, 1, W.wb + kOffW3, kOut, 1);
   g.C = wk.y;
   g.bias = W.w + kOffB3;
-  gemm(g, kEpiBias, gate, st);
+  gemm(g, kEpiBias, nullptr, st);
 }
 
 void mlp_forward(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, hipStream_t st) {
-  forward_gated(W, x, rows, wk, nullptr, true, st);
+  forward(W, x, rows, wk, st);
 }
 
 // --------------------------------------------------------------- backward --
@@ -306,10 +304,33 @@ __global__ void k_adam(float* w, uint16_t* wb, float* m, float* v, const float* 
   wb[i] = f2bf(wi);
 }
 
+// wt = the transposed bfloat16 weights (from wb, so the values are identical)
+__global__ void k_refresh_t(const uint16_t* __restrict__ wb, uint16_t* __restrict__ wt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kWT) return;
+  uint16_t v;
+  if (i < kOffT2) {
+    const int n = i / kFeat, k = i % kFeat;
+    v = wb[kOffW1 + k * kHid + n];
+  } else if (i < kOffT3) {
+    const int n = (i - kOffT2) / kHid, k = (i - kOffT2) % kHid;
+    v = wb[kOffW2 + k * kHid + n];
+  } else {
+    const int n = (i - kOffT3) / kHid, k = (i - kOffT3) % kHid;
+    v = n < kOut ? wb[kOffW3 + k * kOut + n] : (uint16_t)0;
+  }
+  wt[i] = v;
+}
+
+static void refresh_t(const MlpWeights& W, hipStream_t st) {
+  hipLaunchKernelGGL(k_refresh_t, dim3((kWT + 255) / 256), dim3(256), 0, st, W.wb, W.wt);
+}
+
 void mlp_adam(const MlpWeights& W, int step, float lr, float b1, float b2, float eps, hipStream_t st) {
   const float c1 = (float)(1.0 - pow((double)b1, step)), c2 = (float)(1.0 - pow((double)b2, step));
   hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, st, W.w, W.wb, W.m, W.v, W.grad, kParams, lr,
                      b1, b2, eps, c1, c2);
+  refresh_t(W, st);
 }
 
 __global__ void k_refresh(const float* w, uint16_t* wb, int n) {
@@ -319,6 +340,7 @@ __global__ void k_refresh(const float* w, uint16_t* wb, int n) {
 
 void mlp_refresh_bf16(const MlpWeights& W, hipStream_t st) {
   hipLaunchKernelGGL(k_refresh, dim3((kParams + 255) / 256), dim3(256), 0, st, W.w, W.wb, kParams);
+  refresh_t(W, st);
 }
 
 // ---------------------------------------------------------------- features --
@@ -415,6 +437,100 @@ void launch_features(const PhysPlan& P, const ClosurePlan& C, bool always, hipSt
   hipLaunchKernelGGL(k_features<256>, dim3((P.na + 3) / 4), dim3(256), 0, st, P, C, always ? 1 : 0);
 }
 
+// ------------------------------------------------------- fused inference --
+
+// One wave per 16 agents: the three layers in registers and a per-wave LDS
+// tile, on the same v_mfma_f32_16x16x32_bf16 sequence as k_gemm (operand k
+// order, k steps of 32 in ascending order, the same epilogues), so fhat is
+// bit-identical to mlp_forward followed by the scaling.  A lane's A fragment
+// is row (lane % 16), k 8 (lane / 16) .. + 7 of the step; its B fragment the
+// same k of column (lane % 16) of the tile, read from the transposed weights
+// as 16 contiguous bytes; the result holds rows 4 (lane / 16) + q, column
+// lane % 16.
+constexpr int kInferWaves = 4;
+constexpr int kHPad = kHid + 8;  // LDS row of a hidden tile (16-byte aligned rows)
+
+// LDS written by some lanes of a wave and read by others: order them
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bf16x8 ld_frag(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+__global__ void __launch_bounds__(kInferWaves * kWave) k_closure_infer(const uint16_t* __restrict__ X, uint32_t rows,
+                                                                     const uint16_t* __restrict__ wt,
+                                                                     const float* __restrict__ w, ClosurePlan C,
+                                                                     float scale) {
+  __shared__ __attribute__((aligned(16))) uint16_t sH[kInferWaves][16][kHPad];
+  if (!C.state[kClNeed]) return;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint32_t r0 = (blockIdx.x * kInferWaves + wave) * 16u;
+  if (r0 >= rows) return;  // whole wave; no block-wide barriers below
+  const int fr = lane & 15, fk = (lane >> 4) * 8, qr = (lane >> 4) * 4;
+  const uint32_t ra = r0 + (uint32_t)fr;  // the row this lane feeds
+  uint16_t(*H)[kHPad] = sH[wave];
+
+  // layer 1: H1 = bf16(gelu(X W1 + b1))
+  f32x4 acc[kHid / 16];
+#pragma unroll
+  for (int j = 0; j < kHid / 16; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < kFeat; k0 += 32) {
+    bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    if (ra < rows) a = ld_frag(X + (size_t)ra * kFeat + k0 + fk);
+#pragma unroll
+    for (int j = 0; j < kHid / 16; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld_frag(wt + kOffT1 + (j * 16 + fr) * kFeat + k0 + fk),
+                                                        acc[j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < kHid / 16; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) H[qr + q][j * 16 + fr] = f2bf(gelu(acc[j][q] + w[kOffB1 + j * 16 + fr]));
+  wave_lds_sync();
+
+  // layer 2: H2 = bf16(gelu(H1 W2 + b2)), written over H1 once it has been read
+#pragma unroll
+  for (int j = 0; j < kHid / 16; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const bf16x8 a = ld_frag(&H[fr][k0 + fk]);
+#pragma unroll
+    for (int j = 0; j < kHid / 16; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld_frag(wt + kOffT2 + (j * 16 + fr) * kHid + k0 + fk),
+                                                        acc[j], 0, 0, 0);
+  }
+  wave_lds_sync();  // every lane has read H1
+#pragma unroll
+  for (int j = 0; j < kHid / 16; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) H[qr + q][j * 16 + fr] = f2bf(gelu(acc[j][q] + w[kOffB2 + j * 16 + fr]));
+  wave_lds_sync();
+
+  // layer 3: y = H2 W3 + b3 (columns 3..15 of the tile are zero weights)
+  f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k0 = 0; k0 < kHid; k0 += 32)
+    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld_frag(&H[fr][k0 + fk]), ld_frag(wt + kOffT3 + fr * kHid + k0 + fk), y,
+                                                0, 0, 0);
+  if (fr >= kOut) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t a = r0 + (uint32_t)(qr + q);
+    if (a < rows) C.fhat[3 * (size_t)a + fr] = C.occ[a] ? (y[q] + w[kOffB3 + fr]) * scale : 0.0f;
+  }
+}
+
+void launch_closure_infer(const MlpWeights& W, const ClosurePlan& C, uint32_t na, hipStream_t st) {
+  if (!na) return;
+  const uint32_t per_block = kInferWaves * 16u;
+  hipLaunchKernelGGL(k_closure_infer, dim3((na + per_block - 1) / per_block), dim3(kInferWaves * kWave), 0, st,
+                     C.feat, na, W.wt, W.w, C, W.scale);
+}
+
 // -------------------------------------------------------------- controller --
 
 // Decides, from the step counter and the current mode, whether this step uses
@@ -432,20 +548,6 @@ __global__ void k_closure_begin(ClosurePlan C) {
 
 void launch_closure_begin(const ClosurePlan& C, hipStream_t st) {
   hipLaunchKernelGGL(k_closure_begin, dim3(1), dim3(64), 0, st, C);
-}
-
-// fhat = y * scale for agents with fluid in their block, else 0
-__global__ void k_closure_apply(ClosurePlan C, const float* y, float scale, uint32_t na) {
-  if (!C.state[kClNeed]) return;
-  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= na) return;
-  const bool occ = C.occ[a] != 0;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) C.fhat[3 * a + k] = occ ? y[3 * a + k] * scale : 0.0f;
-}
-
-void launch_closure_apply(const ClosurePlan& C, const float* y, float scale, uint32_t na, hipStream_t st) {
-  if (na) hipLaunchKernelGGL(k_closure_apply, dim3((na + 255) / 256), dim3(256), 0, st, C, y, scale, na);
 }
 
 // At a check step: rel_rms = sqrt(sum |fhat - F|^2 / sum |F|^2) over all
@@ -488,9 +590,5 @@ void launch_closure_end(const ClosurePlan& C, uint32_t na, hipStream_t st) {
   hipLaunchKernelGGL(k_closure_end, dim3(1), dim3(256), 0, st, C, na);
 }
 
-void mlp_forward_gated(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, const uint32_t* gate,
-                       hipStream_t st) {
-  forward_gated(W, x, rows, wk, gate, false, st);
-}
 
 }  // namespace sph

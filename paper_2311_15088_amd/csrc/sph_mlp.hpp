@@ -40,9 +40,14 @@ struct GemmArgs {
 void launch_gemm(const GemmArgs& g, int epilogue, hipStream_t st);
 
 // Closure weights and optimiser state on the device.
+// Transposed bfloat16 weights for the fused inference kernel: W1^T [128][256],
+// W2^T [128][128], W3^T padded to [16][128] (rows 3..15 zero).
+constexpr int kOffT1 = 0, kOffT2 = kOffT1 + kHid * kFeat, kOffT3 = kOffT2 + kHid * kHid, kWT = kOffT3 + 16 * kHid;
+
 struct MlpWeights {
   float* w;       // [kParams] float32 master weights
   uint16_t* wb;   // [kParams] bfloat16 copy used by the products
+  uint16_t* wt;   // [kWT] transposed bfloat16 copy (fused inference), refreshed with wb
   float* m;       // Adam moments
   float* v;
   float* grad;    // [kParams]
@@ -66,9 +71,6 @@ void mlp_backward(const MlpWeights& W, const uint16_t* x, const float* t, int ro
                   hipStream_t st);
 void mlp_backward_scaled(const MlpWeights& W, const uint16_t* x, const float* t, float tscale, int rows, MlpWork& wk,
                          float* loss_out, hipStream_t st);
-// forward pass whose kernels return at once when *gate == 0 (graph-capturable skip)
-void mlp_forward_gated(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, const uint32_t* gate,
-                       hipStream_t st);
 void mlp_adam(const MlpWeights& W, int step, float lr, float b1, float b2, float eps, hipStream_t st);
 void mlp_refresh_bf16(const MlpWeights& W, hipStream_t st);
 
@@ -89,7 +91,9 @@ struct ClosurePlan {
 
 void launch_features(const PhysPlan& P, const ClosurePlan& C, bool always, hipStream_t st);
 void launch_closure_begin(const ClosurePlan& C, hipStream_t st);
-void launch_closure_apply(const ClosurePlan& C, const float* y, float scale, uint32_t na, hipStream_t st);
+// The closure's per-step inference in one kernel (gated on the controller):
+// fhat = occ ? MLP(features) * scale : 0, bit-identical to mlp_forward.
+void launch_closure_infer(const MlpWeights& W, const ClosurePlan& C, uint32_t na, hipStream_t st);
 void launch_closure_end(const ClosurePlan& C, uint32_t na, hipStream_t st);
 
 }  // namespace sph

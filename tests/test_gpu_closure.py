@@ -146,3 +146,44 @@ def test_training_lowers_error_and_controller_switches():
     for s in (a, b, c):
         s.close()
     cl.close()
+
+
+def _step_matches_predict(sim, cl):
+    """fhat of the last step (fused in-step inference) against Closure.predict on
+    the same features: bit-identical where the agent's block holds fluid, 0 elsewhere."""
+    feats = sim.read(sph.AGENT_FEATURES)
+    fhat = sim.read(sph.AGENT_FORCE_MODEL)
+    pred = torch.zeros((feats.shape[0], 3), dtype=torch.float32, device=DEV)
+    cl.predict(to_dev_bits(feats), pred)
+    pred = pred.cpu().numpy()
+    occ = (feats[:, 0::4] != 0).any(axis=1)
+    assert occ.any() and not occ.all()
+    want = np.where(occ[:, None], pred, np.float32(0.0))
+    np.testing.assert_array_equal(fhat.view(np.uint32), want.view(np.uint32))
+
+
+def test_in_step_inference_equals_predict():
+    # agents in the upper half of the box: some blocks hold fluid, some do not;
+    # a ragged count (not a multiple of 16 or 64)
+    sc = scenes.dam_break("agents", 24, 12, 24, 0.05, (0, 0, 0), (1.2, 0.6, 1.2), 1001, 5e-4, 10,
+                          scenes.SEED0 + 0x907, agents="upper")
+    cl = sph.Closure(scenes.mlp_flat(params_np(11)), force_scale=2.5)
+    sim = sph.create(sc)
+    sim.attach_closure(cl, check_every=2, max_rel_rms=1e30)
+    sim.step(3)
+    assert sim.closure_stats()["surrogate_steps"] >= 1
+    _step_matches_predict(sim, cl)
+    # changed weights (an Adam step, then a direct write) reach the in-step copy
+    feats = sim.read(sph.AGENT_FEATURES)
+    target = np.random.default_rng(5).standard_normal((feats.shape[0], 3)).astype(np.float32)
+    g, _ = cl.gradient(to_dev_bits(feats), torch.from_numpy(target).to(DEV))
+    cl.adam_step(g, 1, lr=1e-2)
+    sim.step(1)
+    _step_matches_predict(sim, cl)
+    w, _ = cl.weights()
+    cl.set_weights(0.5 * w, force_scale=0.75)
+    sim.step(1)
+    _step_matches_predict(sim, cl)
+    sim.attach_closure(None)
+    sim.close()
+    cl.close()
