@@ -54,7 +54,7 @@ FLOP_FORCE_PER_PARTICLE = 30
 # runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scale factors a plain
 # 1 GiB device copy reads on the same counters), averaged over the 1,000 steps
 # this script times; valid only for the kernel sources it was measured on.
-TRAFFIC_FORCE = {"sources_sha256_16": "e7df3de9bed6fc45", "bytes_per_launch": 321.1e6,
+TRAFFIC_FORCE = {"sources_sha256_16": "92bebe4756849b0f", "bytes_per_launch": 314.7e6,
                  "measured_on": "the 1,000 timed steps"}
 FORCE_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
 
@@ -154,6 +154,37 @@ def scale_leg(sph, scenes, torch, args):
             "particle_steps_per_s": sc.n * K / wall, "pair_interactions_per_s": pairs / wall,
             "mean_neighbours": pairs / (K * sc.n), "step_hbm_frac": b_alg * sc.n / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
             "kernel_us_per_step": {k: 1e3 * v / K for k, v in ph.items()}}
+
+
+def search_leg(sph, scenes, torch, args):
+    """The paper's list-based neighbour searches against the tiled gather on the
+    same workload: per-phase times, with the sort plus the list build taken as
+    the neighbour search."""
+    sc = scenes.config1()
+    stream = torch.cuda.current_stream().cuda_stream
+    K = args.search_steps
+    out = {"workload": "dam break 128x64x128 = 1,048,576 particles + 1,024 boids, h=0.02, dt=2e-4", "steps": K}
+    names = {sph.SEARCH_TILES: "tiled_gather", sph.SEARCH_SORTED_LIST: "sorted_list",
+             sph.SEARCH_BUCKET_LIST: "bucket_list"}
+    search_phases = ("key_count", "scan_reduce", "scan_apply", "scatter", "fixup_tile_list")
+    for mode, name in names.items():
+        sim = sph.create(sc, stream=stream)
+        if mode != sph.SEARCH_TILES:
+            sim.set_search(mode)
+        sim.step_profiled(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = sim.step_profiled(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        us = {k: 1e3 * v / K for k, v in ph.items()}
+        out[name] = {"ms_per_step": 1e3 * wall / K, "us_per_step": us,
+                     "neighbour_search_us": sum(us[k] for k in search_phases),
+                     "fluid_passes_us": us["density"] + us["force_integrate"]}
+        log(f"[bench] search {name}: {1e3 * wall / K:.4f} ms/step, neighbour search "
+            f"{out[name]['neighbour_search_us']:.1f} us, density + force {out[name]['fluid_passes_us']:.1f} us")
+    return out
 
 
 def batched_leg(sph, scenes, torch, args):
@@ -272,6 +303,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--closure-steps", type=int, default=1000)
+    ap.add_argument("--search", action="store_true", help="add the list-based neighbour-search comparison")
+    ap.add_argument("--search-steps", type=int, default=100)
+    ap.add_argument("--search-mode", type=int, default=0, help="neighbour search of --plain-steps (0, 1, 2)")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the HBM "
                          "byte counters of a profiler against a kernel of known traffic) and exit")
@@ -309,6 +343,8 @@ def main():
         sim = sph.create(sc)
         if args.tuning:
             sim.set_tuning(*[int(t) for t in args.tuning.split(",")])
+        if args.search_mode:
+            sim.set_search(args.search_mode)
         sim.step(args.plain_steps)
         torch.cuda.synchronize()
         log(f"[bench] {args.plain_steps} plain steps done, tuning {sim.tuning()}")
@@ -422,6 +458,8 @@ def main():
         result["batched"] = batched_leg(sph, scenes, torch, args)
     if args.closure:
         result["closure"] = closure_leg(sph, scenes, torch, args)
+    if args.search:
+        result["search"] = search_leg(sph, scenes, torch, args)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)

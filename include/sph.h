@@ -97,7 +97,13 @@ typedef enum {
   SPH_AGENT_CELL_OFFSETS = 17,
   SPH_PAIR_COUNT = 18,  /* uint64 [1]: sum of SPH_NBR_COUNT over all steps since create */
   SPH_AGENT_FEATURES = 19,   /* bfloat16 bits, uint16 [a][256]: closure features of the last step */
-  SPH_AGENT_FORCE_MODEL = 20 /* float32 [a][3]: closure (surrogate) force of the last step */
+  SPH_AGENT_FORCE_MODEL = 20, /* float32 [a][3]: closure (surrogate) force of the last step */
+  /* neighbour-list forms only (sph_search_set), sorted order of the last step,
+     entries are sorted indices and every list includes the particle itself */
+  SPH_NBR_LIST_COUNTS = 21,  /* uint32 [n]: entries of each particle's list */
+  SPH_NBR_LIST_OFFSETS = 22, /* uint32 [n + 1]: first entry of each list (sorted list only) */
+  SPH_NBR_LIST = 23          /* uint32 [list capacity]: the list buffer (bucket list: 27 x capacity
+                                entries per particle, the first SPH_NBR_LIST_COUNTS of them valid) */
 } sph_field;
 
 typedef struct sph_info {
@@ -170,6 +176,32 @@ sph_status sph_tuning_get(const sph_ctx* ctx, sph_tuning* out);
 /* Number of kernel variants of a form, and the name of one (NULL if out of range). */
 int32_t sph_variant_count(int32_t fused);
 const char* sph_variant_name(int32_t fused, int32_t variant);
+
+/* Neighbour search of the fluid passes.  The paper describes two list-based
+   searches: a hash grid of fixed-capacity cell buckets filled through an
+   atomic slot per particle, with a fixed-capacity list per particle over the
+   27 surrounding cells ("Neighbor Search" section), and a search on the
+   counting-sorted particles that counts each particle's neighbours, scans
+   the counts into offsets and fills a packed list ("Neighbor Search with
+   Sorting" section).  This library's own form gathers candidates cell row by
+   cell row into LDS and keeps no list; the two list forms are kept beside it
+   as ablations and run the density and force passes over their lists.
+     mode 0  tiled cell gather (default; bucket_capacity, list_per_particle unused)
+     mode 1  sorted list: list_per_particle entries per particle are reserved
+             (0: 64), 2^32 - 1 in all at most
+     mode 2  bucket list: bucket_capacity particles per cell (0: 32); the list
+             holds 27 x bucket_capacity entries per particle
+   The sorted list takes each particle's candidates in the tiled form's order,
+   so every result is bit-identical to mode 0; the bucket list takes a cell's
+   particles in the order its atomics gave, so sums may differ by rounding.
+   A list form allocates its buffers here (the context owns them) and runs one
+   launch per phase; sph_autotune then returns SPH_ESTATE.  sph_step,
+   sph_step_profiled and sph_step_timed synchronise the stream at their end in
+   a list form and return SPH_ECAPACITY if a bucket or the list buffer was too
+   small in any of their steps; the state is then not valid (entries past the
+   capacity were left out, never written out of bounds).  Drops a captured
+   graph.  Synchronises the stream. */
+sph_status sph_search_set(sph_ctx* ctx, int32_t mode, int32_t bucket_capacity, int32_t list_per_particle);
 
 /* ---------------------------------------------------------------------------
    Learned coupling closure.  A small MLP (256 -> 128 -> 128 -> 3, GELU after

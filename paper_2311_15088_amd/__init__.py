@@ -27,7 +27,10 @@ CLOSURE_PARAMS, CLOSURE_FEATURES = 49795, 256
 # fields (sph_field)
 POS, VEL, AGENT_POS, AGENT_VEL, DENSITY, NBR_COUNT, CELL_KEY, ACC_INT, ACC_COUPLE, TOUCHED, \
     AGENT_FORCE, AGENT_STEER, AGENT_COUNTS, SORTED_IDS, CELL_OFFSETS, AGENT_KEY, AGENT_SORTED_IDS, \
-    AGENT_CELL_OFFSETS, PAIR_COUNT, AGENT_FEATURES, AGENT_FORCE_MODEL = range(21)
+    AGENT_CELL_OFFSETS, PAIR_COUNT, AGENT_FEATURES, AGENT_FORCE_MODEL, NBR_LIST_COUNTS, NBR_LIST_OFFSETS, \
+    NBR_LIST = range(24)
+# neighbour search of the fluid passes (sph_search_set)
+SEARCH_TILES, SEARCH_SORTED_LIST, SEARCH_BUCKET_LIST = 0, 1, 2
 
 _FIELD_DTYPE = {
     POS: (np.float32, 3), VEL: (np.float32, 3), AGENT_POS: (np.float32, 3), AGENT_VEL: (np.float32, 3),
@@ -36,7 +39,8 @@ _FIELD_DTYPE = {
     AGENT_STEER: (np.float32, 3), AGENT_COUNTS: (np.uint32, 4), SORTED_IDS: (np.uint32, 1),
     CELL_OFFSETS: (np.uint32, 1), AGENT_KEY: (np.uint32, 1), AGENT_SORTED_IDS: (np.uint32, 1),
     AGENT_CELL_OFFSETS: (np.uint32, 1), PAIR_COUNT: (np.uint64, 1), AGENT_FEATURES: (np.uint16, 256),
-    AGENT_FORCE_MODEL: (np.float32, 3),
+    AGENT_FORCE_MODEL: (np.float32, 3), NBR_LIST_COUNTS: (np.uint32, 1), NBR_LIST_OFFSETS: (np.uint32, 1),
+    NBR_LIST: (np.uint32, 1),
 }
 
 
@@ -150,6 +154,8 @@ def lib() -> ctypes.CDLL:
         L.sph_tuning_get.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.sph_variant_count.restype = i32
         L.sph_variant_count.argtypes = [i32]
+        L.sph_search_set.restype = ctypes.c_int
+        L.sph_search_set.argtypes = [vp, i32, i32, i32]
         L.sph_variant_name.restype = ctypes.c_char_p
         L.sph_variant_name.argtypes = [i32, i32]
         L.sph_closure_create.restype = ctypes.c_int
@@ -295,6 +301,10 @@ class Simulation:
         """Execution form: fused (0/1), kernel variant, cells per fluid tile along x."""
         t = Tuning(int(fused), int(variant), int(tile_x), 0.0)
         _check(lib().sph_tuning_set(self._ctx, ctypes.byref(t)), self._ctx)
+
+    def set_search(self, mode: int, bucket_capacity: int = 0, list_per_particle: int = 0) -> None:
+        """Neighbour search of the fluid passes: SEARCH_TILES, SEARCH_SORTED_LIST or SEARCH_BUCKET_LIST."""
+        _check(lib().sph_search_set(self._ctx, int(mode), int(bucket_capacity), int(list_per_particle)), self._ctx)
 
     def tuning(self) -> Dict:
         t = Tuning()

@@ -524,9 +524,11 @@ sph_status sph_ctx_closure_buffers(sph_ctx* ctx) {
   return SPH_OK;
 }
 
+static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+
 sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
-  // the closure and feature collection run between phases: per-phase launches
-  if (ctx->fused && !ctx->closure && !ctx->features) {
+  // the closure, feature collection and the list forms run per-phase launches
+  if (ctx->fused && !ctx->closure && !ctx->features && ctx->list.mode == kSearchTiles) {
     FusedPlan F;
     F.sort = ctx->sort;
     F.phys = ctx->phys;
@@ -534,15 +536,8 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
     F.abort_flag = ctx->d_abort;
     for (int32_t k = 0; k < n_steps; ++k) launch_step_fused(F, ctx->fused_variant, st);
   } else {
-    for (int32_t k = 0; k < n_steps; ++k) {
-      for (int ph = 0; ph < kSortPhases - 1; ++ph) launch_sort_phase(ctx->sort, ph, st);
-      launch_fixup_tiles(ctx->sort, ctx->phys, st);
-      launch_density(ctx->phys, st);
-      sph_ctx_closure_phase(ctx, st);
-      launch_agents(ctx->phys, st);
-      launch_force(ctx->phys, st);
-      sph_ctx_closure_end(ctx, st);
-    }
+    for (int32_t k = 0; k < n_steps; ++k)
+      for (int p = 0; p < kStepPhases; ++p) launch_phase(ctx, p, st);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, SPH_EHIP, "kernel launch: %s", hipGetErrorString(e));
@@ -551,17 +546,43 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
 
 // Phase p of one step (p < kStepPhases), in launch order.  start / stop:
 // optional events at the fluid kernels' own start and end.
-static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr) {
-  if (p < kSortPhases - 1) launch_sort_phase(ctx->sort, p, st);
-  else if (p == kSortPhases - 1) launch_fixup_tiles(ctx->sort, ctx->phys, st);
-  else if (p == kSortPhases) launch_density(ctx->phys, st, start, stop);
-  else if (p == kSortPhases + 1) {
+// A list form builds its lists in the fix-up's phase and runs its own
+// density and force kernels in theirs.
+static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+  const bool lists = ctx->list.mode != kSearchTiles;
+  if (p < kSortPhases - 1) {
+    launch_sort_phase(ctx->sort, p, st);
+  } else if (p == kSortPhases - 1) {
+    launch_fixup_tiles(ctx->sort, ctx->phys, st, !lists);
+    if (lists) launch_list_build(ctx->phys, ctx->list, st);
+  } else if (p == kSortPhases) {
+    if (lists) launch_list_density(ctx->phys, ctx->list, st, start, stop);
+    else launch_density(ctx->phys, st, start, stop);
+  } else if (p == kSortPhases + 1) {
     sph_ctx_closure_phase(ctx, st);
     launch_agents(ctx->phys, st);
   } else {
-    launch_force(ctx->phys, st, start, stop);
+    if (lists) launch_list_force(ctx->phys, ctx->list, st, start, stop);
+    else launch_force(ctx->phys, st, start, stop);
     sph_ctx_closure_end(ctx, st);
   }
+}
+
+// List forms: the sticky overflow flags of the steps enqueued so far.  A set
+// flag means some list or bucket dropped entries, so those steps are not valid.
+static sph_status check_list_status(sph_ctx* ctx) {
+  if (ctx->list.mode == kSearchTiles) return SPH_OK;
+  uint32_t f[kListStatusWords] = {0u, 0u};
+  HIPCHK(hipMemcpyAsync(f, ctx->list.status, sizeof f, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!f[kBucketOverflow] && !f[kListOverflow]) return SPH_OK;
+  HIPCHK(hipMemsetAsync(ctx->list.status, 0, sizeof f, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (f[kBucketOverflow])
+    return fail(ctx, SPH_ECAPACITY, "a cell held more than the bucket capacity (%u particles); the state is not valid",
+                ctx->list.cap);
+  return fail(ctx, SPH_ECAPACITY, "the neighbour lists needed more than %llu entries; the state is not valid",
+              (unsigned long long)ctx->list.list_cap);
 }
 
 // Phases timed by events at their kernel's own start and end (the others by
@@ -755,6 +776,9 @@ int64_t field_bytes(const sph_ctx* ctx, int32_t f) {
     case SPH_PAIR_COUNT: return 8;
     case SPH_AGENT_FEATURES: return 2 * kFeat * A;
     case SPH_AGENT_FORCE_MODEL: return 12 * A;
+    case SPH_NBR_LIST_COUNTS: return 4 * N;
+    case SPH_NBR_LIST_OFFSETS: return 4 * (N + 1);
+    case SPH_NBR_LIST: return 4 * (int64_t)ctx->list.list_cap;
     default: return -1;
   }
 }
@@ -770,6 +794,11 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
   if (is_diag && !ctx->diag) return fail(ctx, SPH_ESTATE, "diagnostics were not enabled (SPH_FLAG_DIAGNOSTICS)");
   if ((field == SPH_AGENT_FEATURES || field == SPH_AGENT_FORCE_MODEL) && !ctx->cl_arena)
     return fail(ctx, SPH_ESTATE, "features are computed only with SPH_FLAG_FEATURES or an attached closure");
+  const bool is_list = field == SPH_NBR_LIST_COUNTS || field == SPH_NBR_LIST_OFFSETS || field == SPH_NBR_LIST;
+  if (is_list && ctx->list.mode == kSearchTiles)
+    return fail(ctx, SPH_ESTATE, "no neighbour lists: the search mode is the tiled gather");
+  if (field == SPH_NBR_LIST_OFFSETS && ctx->list.mode != kSearchSortedList)
+    return fail(ctx, SPH_ESTATE, "list offsets exist for the sorted list only (bucket list: 27 x capacity per particle)");
   if (need == 0) return SPH_OK;
   hipStream_t st = ctx->stream;
   if (!ctx->staging || ctx->staging_bytes < (size_t)need) {
@@ -845,6 +874,15 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
       break;
     case SPH_AGENT_FORCE_MODEL:
       HIPCHK(hipMemcpyAsync(out, ctx->cplan.fhat, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_NBR_LIST_COUNTS:
+      HIPCHK(hipMemcpyAsync(out, ctx->list.lcnt, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_NBR_LIST_OFFSETS:
+      HIPCHK(hipMemcpyAsync(out, ctx->list.loff, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_NBR_LIST:
+      HIPCHK(hipMemcpyAsync(out, ctx->list.list, (size_t)need, hipMemcpyDeviceToDevice, st));
       break;
   }
   HIPCHK(hipGetLastError());
@@ -1098,6 +1136,8 @@ sph_status sph_step(sph_ctx* ctx, int32_t n_steps) {
   }
   if (s != SPH_OK) return s;
   ctx->steps += n_steps;
+  s = check_list_status(ctx);
+  if (s != SPH_OK) return s;
   if (ctx->check_finite) return check_finite(ctx);
   return SPH_OK;
 }
@@ -1136,14 +1176,16 @@ sph_status sph_step_profiled(sph_ctx* ctx, int32_t n_steps, double* phase_ms, in
   if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
   if (n_phases < kStepPhases) return fail(ctx, SPH_EINVAL, "phase_ms must hold %d entries", kStepPhases);
   for (int p = 0; p < n_phases; ++p) phase_ms[p] = 0.0;
-  return sph_profile_impl(ctx, n_steps, phase_ms, true);
+  sph_status s = sph_profile_impl(ctx, n_steps, phase_ms, true);
+  return s != SPH_OK ? s : check_list_status(ctx);
 }
 
 sph_status sph_step_timed(sph_ctx* ctx, int32_t n_steps, double* kernel_ms) {
   if (!ctx || !kernel_ms) return fail(ctx, SPH_EINVAL, "NULL argument");
   if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
   kernel_ms[0] = kernel_ms[1] = 0.0;
-  return sph_profile_impl(ctx, n_steps, kernel_ms, false);
+  sph_status s = sph_profile_impl(ctx, n_steps, kernel_ms, false);
+  return s != SPH_OK ? s : check_list_status(ctx);
 }
 
 const char* sph_phase_name(int32_t phase) {
@@ -1191,6 +1233,7 @@ void sph_destroy(sph_ctx* ctx) {
   if (ctx->staging) (void)hipFree(ctx->staging);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->cl_arena) (void)hipFree(ctx->cl_arena);
+  if (ctx->list_arena) (void)hipFree(ctx->list_arena);
   delete ctx;
 }
 
@@ -1198,6 +1241,7 @@ const char* sph_last_error(const sph_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 sph_status sph_autotune(sph_ctx* ctx, int32_t steps_per_trial, sph_tuning* best) {
   if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  if (ctx->list.mode != kSearchTiles) return fail(ctx, SPH_ESTATE, "the forms tuned are those of the tiled gather");
   return autotune_impl(ctx, steps_per_trial, best);
 }
 
@@ -1216,6 +1260,58 @@ int32_t sph_variant_count(int32_t fused) { return fused ? fused_variant_count() 
 
 const char* sph_variant_name(int32_t fused, int32_t variant) {
   return fused ? fused_variant_name(variant) : fluid_variant_name(variant);
+}
+
+sph_status sph_search_set(sph_ctx* ctx, int32_t mode, int32_t bucket_capacity, int32_t list_per_particle) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  if (mode < kSearchTiles || mode > kSearchBucketList) return fail(ctx, SPH_EINVAL, "unknown search mode %d", mode);
+  if (bucket_capacity < 0 || bucket_capacity > 4096 || list_per_particle < 0 || list_per_particle > 4096)
+    return fail(ctx, SPH_EINVAL, "bucket_capacity and list_per_particle must be in [0, 4096]");
+  sph_status st = drop_graph(ctx);
+  if (st != SPH_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));  // earlier steps may still use the old lists
+  if (ctx->list_arena) HIPCHK(hipFree(ctx->list_arena));
+  ctx->list_arena = nullptr;
+  ctx->list = ListPlan{};
+  ctx->list.mode = kSearchTiles;
+  if (mode == kSearchTiles) return SPH_OK;
+
+  const uint64_t nf = ctx->N, cells = ctx->C;
+  const uint32_t cap = mode == kSearchBucketList ? (uint32_t)(bucket_capacity ? bucket_capacity : 32) : 0u;
+  const uint64_t entries = mode == kSearchSortedList ? nf * (uint64_t)(list_per_particle ? list_per_particle : 64)
+                                                     : nf * 27u * cap;
+  if (mode == kSearchSortedList && entries > 0xffffffffull)
+    return fail(ctx, SPH_ECAPACITY, "the sorted list's offsets are 32-bit: at most 2^32 - 1 entries");
+  const uint32_t chunks = mode == kSearchSortedList ? list_scan_chunks(ctx->N) : 0u;
+  const uint64_t sz[] = {4 * nf, mode == kSearchSortedList ? 4 * (nf + 1) : 0, 4ull * chunks, 4 * entries,
+                         cap ? 4 * cells : 0, 4 * cells * cap, 4ull * kListStatusWords};
+  constexpr int kBufs = (int)(sizeof sz / sizeof sz[0]);
+  uint64_t tot = 0;
+  for (uint64_t b : sz) tot += align_up(b, 256);
+  char* arena = nullptr;
+  hipError_t e = hipMalloc((void**)&arena, (size_t)tot);
+  if (e != hipSuccess) return fail(ctx, SPH_ENOMEM, "neighbour-list buffers (%llu bytes): %s",
+                                   (unsigned long long)tot, hipGetErrorString(e));
+  ListPlan L{};
+  uint32_t** dst[kBufs] = {&L.lcnt, &L.loff, &L.lsum, &L.list, &L.bcnt, &L.bucket, &L.status};
+  char* p = arena;
+  for (int k = 0; k < kBufs; ++k) {
+    *dst[k] = sz[k] ? (uint32_t*)p : nullptr;
+    p += align_up(sz[k], 256);
+  }
+  e = hipMemsetAsync(arena, 0, (size_t)tot, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(arena);
+    return fail(ctx, SPH_EHIP, "neighbour-list buffers: %s", hipGetErrorString(e));
+  }
+  L.mode = mode;
+  L.cap = cap;
+  L.list_cap = entries;
+  L.ncells = (uint32_t)cells;
+  ctx->list = L;
+  ctx->list_arena = arena;
+  return SPH_OK;
 }
 
 }  // extern "C"

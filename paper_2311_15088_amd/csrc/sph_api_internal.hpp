@@ -78,6 +78,10 @@ struct sph_ctx {
   bool features = false;     // compute features every step (training-data collection)
   sph::ClosurePlan cplan{};  // buffers allocated on first use
   char* cl_arena = nullptr;
+
+  // neighbour-list forms of the fluid passes (mode kSearchTiles: none)
+  sph::ListPlan list{};
+  char* list_arena = nullptr;
 };
 
 sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vector<int64_t>& n,

@@ -86,11 +86,39 @@ int fluid_item_max(int fused, int variant);
 const char* fluid_variant_name(int v);
 // The sort's fix-up and the fluid passes' work-item list in one launch (the
 // list needs only the cell offsets, so it overlaps the fix-up).
-void launch_fixup_tiles(const SortPlan& S, const PhysPlan& P, hipStream_t st);
+// with_tiles = false: the fix-up alone (the list forms need no work items)
+void launch_fixup_tiles(const SortPlan& S, const PhysPlan& P, hipStream_t st, bool with_tiles = true);
 // start / stop: optional events recorded at the fluid kernel's own start and end
 void launch_density(const PhysPlan& P, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 void launch_agents(const PhysPlan& P, hipStream_t st);
 void launch_force(const PhysPlan& P, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+
+// Neighbour-list forms of the fluid passes (the paper's list-based neighbour
+// search), kept beside the tiled gather as ablations.  Mode: the tiled gather,
+// the sorted list (count, scan, fill on the counting-sorted particles) or the
+// bucket list (fixed-capacity cell buckets, 27 x capacity entries per particle).
+constexpr int kSearchTiles = 0, kSearchSortedList = 1, kSearchBucketList = 2;
+constexpr int kBucketOverflow = 0, kListOverflow = 1, kListStatusWords = 2;
+struct ListPlan {
+  int mode;
+  uint32_t cap;          // bucket list: particles per cell bucket
+  uint64_t list_cap;     // entries of the list buffer
+  uint32_t* lcnt;        // [nf] list length per particle (the particle itself included)
+  uint32_t* loff;        // [nf + 1] sorted list: first entry of each particle
+  uint32_t* lsum;        // sorted list: scan chunk sums
+  uint32_t* list;        // sorted indices: packed (sorted list) or [nf][27 cap] (bucket list)
+  uint32_t* bcnt;        // [ncells] bucket fill counts
+  uint32_t* bucket;      // [ncells][cap]
+  uint32_t ncells;       // fluid cells of all scenes (scene s from its cbase)
+  uint32_t* status;      // [kListStatusWords] sticky overflow flags
+};
+uint32_t list_scan_chunks(uint32_t n);
+// the list of this step (after the sort's fix-up), the passes over it
+void launch_list_build(const PhysPlan& P, const ListPlan& L, hipStream_t st);
+void launch_list_density(const PhysPlan& P, const ListPlan& L, hipStream_t st, hipEvent_t start = nullptr,
+                         hipEvent_t stop = nullptr);
+void launch_list_force(const PhysPlan& P, const ListPlan& L, hipStream_t st, hipEvent_t start = nullptr,
+                       hipEvent_t stop = nullptr);
 
 // One persistent launch per step (all phases, grid-wide barriers).
 constexpr int kFusedBD = 256;

@@ -105,8 +105,8 @@ static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st, hipEvent
   else (void)hipLaunchKernel(fn, dim3(g), dim3(bd), args, 0, st);
 }
 
-void launch_fixup_tiles(const SortPlan& S, const PhysPlan& P, hipStream_t st) {
-  const uint32_t tb = P.nf ? (P.ntiles + 255) / 256 : 0u;
+void launch_fixup_tiles(const SortPlan& S, const PhysPlan& P, hipStream_t st, bool with_tiles) {
+  const uint32_t tb = (P.nf && with_tiles) ? (P.ntiles + 255) / 256 : 0u;
   if (tb + S.nblocks)
     hipLaunchKernelGGL(k_fixup_tiles, dim3(tb + S.nblocks), dim3(256), 0, st, S.sets, S.nsets, S.bprefix, tb, P);
 }

@@ -1,0 +1,145 @@
+"""The paper's list-based neighbour searches (sph_search_set) on the GPU: the
+lists against the oracle's (oracle/nlist.py), steps against the oracle and
+against the tiled gather, and the capacity errors."""
+import numpy as np
+import pytest
+
+import paper_2311_15088_amd as sph
+from oracle import nlist
+from paper_2311_15088_amd import scenes
+from test_gpu_parity import chained_parity, state
+
+pytestmark = pytest.mark.gpu
+
+LISTS = (sph.SEARCH_SORTED_LIST, sph.SEARCH_BUCKET_LIST)
+EXACT = (sph.POS, sph.VEL, sph.DENSITY, sph.NBR_COUNT, sph.AGENT_POS, sph.AGENT_VEL, sph.SORTED_IDS, sph.PAIR_COUNT)
+
+
+def _run(sc, steps, search, **kw):
+    sim = sph.create(sc)
+    if search != sph.SEARCH_TILES:
+        sim.set_search(search, **kw)
+    sim.step(steps)
+    out = {f: sim.read(f) for f in EXACT}
+    sim.close()
+    return out
+
+
+def test_lists_match_oracle():
+    sc = scenes.small_dam(nx=13, ny=7, nz=11, n_agents=37, agents="inside")
+    want = nlist.neighbour_lists(sc.params, sc.x)
+    order = nlist.sorted_state(sc.params, sc.x)["order"]
+    cells = nlist.sorted_state(sc.params, sc.x)["cell"]
+    for mode in LISTS:
+        print(f"[lists] mode {mode} n={sc.n}", flush=True)
+        sim = sph.create(sc)
+        sim.set_search(mode, bucket_capacity=24)
+        sim.step(1)
+        np.testing.assert_array_equal(sim.read(sph.SORTED_IDS), order)
+        cnt = sim.read(sph.NBR_LIST_COUNTS)
+        buf = sim.read(sph.NBR_LIST)
+        np.testing.assert_array_equal(cnt, [len(w) for w in want])
+        if mode == sph.SEARCH_SORTED_LIST:
+            off = sim.read(sph.NBR_LIST_OFFSETS)
+            assert off[0] == 0 and np.array_equal(np.diff(off.astype(np.int64)), cnt)
+            for i, w in enumerate(want):
+                np.testing.assert_array_equal(buf[off[i]:off[i + 1]], w)
+        else:
+            stride = 27 * 24
+            assert buf.size == sc.n * stride
+            for i, w in enumerate(want):
+                got = buf[i * stride:i * stride + cnt[i]]
+                # the same set; cells in (z, y, x) order, a cell's particles in slot order
+                np.testing.assert_array_equal(np.sort(got), np.sort(w))
+                d = cells[got] - cells[i]
+                rank = (d[:, 2] + 1) * 9 + (d[:, 1] + 1) * 3 + (d[:, 0] + 1)
+                assert np.all(np.diff(rank) >= 0)
+        sim.close()
+
+
+def test_sorted_list_is_bit_identical_to_tiles():
+    for sc in (scenes.config0c(), scenes.small_dam(nx=13, ny=7, nz=11, n_agents=37, agents="inside")):
+        ref = _run(sc, 6, sph.SEARCH_TILES)
+        got = _run(sc, 6, sph.SEARCH_SORTED_LIST)
+        for f in EXACT:
+            np.testing.assert_array_equal(got[f], ref[f], err_msg=f"field {f} of {sc.name}")
+
+
+def test_bucket_list_matches_tiles_up_to_rounding():
+    sc = scenes.config0c()
+    ref1 = _run(sc, 1, sph.SEARCH_TILES)
+    got1 = _run(sc, 1, sph.SEARCH_BUCKET_LIST)
+    # one step: the same neighbour sets and order; sums differ by rounding at most
+    for f in (sph.NBR_COUNT, sph.SORTED_IDS, sph.PAIR_COUNT):
+        np.testing.assert_array_equal(got1[f], ref1[f])
+    rho_err = np.max(np.abs(got1[sph.DENSITY] - ref1[sph.DENSITY]) / ref1[sph.DENSITY])
+    assert rho_err < 1e-5
+    x_err = np.max(np.abs(got1[sph.POS] - ref1[sph.POS]))
+    assert x_err < 1e-6 * float(np.max(np.abs(ref1[sph.POS])))
+
+
+@pytest.mark.parametrize("mode", LISTS)
+def test_list_forms_against_oracle(mode):
+    worst = chained_parity(scenes.small_dam(nx=13, ny=7, nz=11, n_agents=37, agents="inside"), 3, search=mode)
+    assert worst["rho"] < 1e-4
+
+
+def test_list_forms_batched_and_graph():
+    specs = scenes.batched_specs(4, n_range=(300, 2500), a_range=(2, 20))
+    scs = [scenes.batched_scene(sp, k) for k, sp in enumerate(specs)]
+    ref = sph.create_batch(scs)
+    ref.step(4)
+    for mode in LISTS:
+        bat = sph.create_batch(scs)
+        bat.set_search(mode)
+        bat.capture(2)
+        bat.step(2)  # graph replays
+        bat.step(2)
+        for f in (sph.NBR_COUNT, sph.SORTED_IDS):
+            np.testing.assert_array_equal(bat.read(f), ref.read(f))
+        x, _, y, _ = state(bat)
+        xr, _, yr, _ = state(ref)
+        if mode == sph.SEARCH_SORTED_LIST:
+            np.testing.assert_array_equal(x, xr)
+            np.testing.assert_array_equal(y, yr)
+        else:
+            assert np.max(np.abs(x - xr)) < 1e-5
+        bat.close()
+    ref.close()
+
+
+def test_capacities_and_invalid_use():
+    sc = scenes.small_dam()
+    sim = sph.create(sc)
+    with pytest.raises(sph.SphError) as e:
+        sim.read(sph.NBR_LIST)
+    assert e.value.status == sph.ESTATE
+    for bad in ((3, 0, 0), (-1, 0, 0), (1, -1, 0), (2, 5000, 0), (1, 0, 5000)):
+        with pytest.raises(sph.SphError) as e:
+            sim.set_search(*bad)
+        assert e.value.status == sph.EINVAL
+    # a bucket of 2 particles: cells hold about 8 -> flagged, nothing written past the bucket
+    sim.set_search(sph.SEARCH_BUCKET_LIST, bucket_capacity=2)
+    with pytest.raises(sph.SphError) as e:
+        sim.step(1)
+    assert e.value.status == sph.ECAPACITY
+    with pytest.raises(sph.SphError) as e:
+        sim.read(sph.NBR_LIST_OFFSETS)
+    assert e.value.status == sph.ESTATE
+    with pytest.raises(sph.SphError) as e:
+        sim.autotune(1)
+    assert e.value.status == sph.ESTATE
+    sim.close()
+    # two list entries per particle: the lists need about 25 each
+    sim = sph.create(sc)
+    sim.set_search(sph.SEARCH_SORTED_LIST, list_per_particle=2)
+    with pytest.raises(sph.SphError) as e:
+        sim.step(1)
+    assert e.value.status == sph.ECAPACITY
+    # back to the tiled form: the list buffers are released (the state of the
+    # flagged step is not valid, so it is not stepped further)
+    sim.set_search(sph.SEARCH_TILES)
+    with pytest.raises(sph.SphError) as e:
+        sim.read(sph.NBR_LIST_COUNTS)
+    assert e.value.status == sph.ESTATE
+    sim.close()

@@ -31,9 +31,11 @@ def state(sim):
     return sim.read(sph.POS), sim.read(sph.VEL), sim.read(sph.AGENT_POS), sim.read(sph.AGENT_VEL)
 
 
-def chained_parity(sc, steps, fs=None, as_=None, nbr_mode=0):
-    print(f"[parity] scene {sc.name} n={sc.n} a={sc.n_agents} steps={steps}", flush=True)
+def chained_parity(sc, steps, fs=None, as_=None, nbr_mode=0, search=sph.SEARCH_TILES):
+    print(f"[parity] scene {sc.name} n={sc.n} a={sc.n_agents} steps={steps} search={search}", flush=True)
     sim = sph.create(sc, flags=sph.FLAG_DIAGNOSTICS)
+    if search != sph.SEARCH_TILES:
+        sim.set_search(search)
     x, v, y, u = sc.x, sc.v, sc.y, sc.u
     worst = {}
     for k in range(steps):

@@ -405,3 +405,46 @@ def test_agent_speed_limits():
     # u' = 0.4 + 0.25 * (-0.8) = 0.2 < v_min -> rescaled to 0.25
     np.testing.assert_allclose(r2["u1"][0], [0.25, 0, 0], rtol=1e-6)
     assert np.all(np.isfinite(r["u1"][:2]))
+
+
+# ---- materialised neighbour lists (oracle/nlist.py) -------------------------
+
+def test_neighbour_lists_on_a_lattice():
+    """Spacing 0.55 h: the neighbours within h are exactly the 26 lattice
+    neighbours at one step per axis (sqrt(3) 0.55 h < h < 2 x 0.55 h), so a list
+    holds 27 entries inside, 8 at a corner, 12 on an edge and 18 on a face."""
+    from oracle import nlist
+    h = 0.05
+    s = 0.55 * h
+    p = _params(h)
+    x = scenes.lattice(6, 6, 6, s, (0.1, 0.1, 0.1)).astype(np.float32)
+    lists = nlist.neighbour_lists(p, x)
+    st = nlist.sorted_state(p, x)
+    ids = st["order"]
+    site = np.stack([ids % 6, (ids // 6) % 6, ids // 36], axis=1)  # lattice index of each sorted particle
+    on_edge = ((site == 0) | (site == 5)).sum(axis=1)  # axes on which the site is at the lattice's end
+    want = {0: 27, 1: 18, 2: 12, 3: 8}
+    for i, lst in enumerate(lists):
+        assert len(lst) == want[int(on_edge[i])]
+        assert i in lst
+        # every entry one lattice step away at most, per axis
+        assert np.abs(site[lst] - site[i]).max() <= 1
+
+
+def test_neighbour_lists_agree_with_brute_force_and_are_ordered():
+    """Against the C oracle's brute-force neighbour counts (a separate
+    implementation of the same predicate): one more entry (the particle
+    itself); entries unique, in halo-row order, then in sorted order."""
+    from oracle import nlist
+    sc = scenes.small_dam()
+    lists = nlist.neighbour_lists(sc.params, sc.x)
+    st = nlist.sorted_state(sc.params, sc.x)
+    r = oracle.step(sc.params, sc.x, sc.v, sc.y, sc.u)
+    np.testing.assert_array_equal(np.array([len(l) for l in lists]), r["nbr"][st["order"]] + 1)
+    c = st["cell"]
+    for i, lst in enumerate(lists):
+        assert len(set(lst.tolist())) == len(lst) and i in lst
+        d = c[lst] - c[i]
+        assert np.abs(d).max() <= 1
+        rank = ((d[:, 2] + 1) * 3 + (d[:, 1] + 1)).astype(np.int64) * len(c) + lst
+        assert np.all(np.diff(rank) > 0)
