@@ -187,6 +187,37 @@ def search_leg(sph, scenes, torch, args):
     return out
 
 
+def voxel_leg(sph, scenes, torch, args):
+    """Voxel density at cube corners on the 1M-particle workload (corner spacing
+    h/2, neighbourhood radius h, particle radius h/4): the step with and without
+    the voxel kernel (the phase events time the density kernel itself, so the
+    voxel kernel shows in the step time)."""
+    sc = scenes.config1()
+    h = sc.params["h"]
+    stream = torch.cuda.current_stream().cuda_stream
+    K = args.search_steps
+    out = {"workload": "dam break 128x64x128 = 1,048,576 particles, box 3x1x3, corners every h/2, R = h, r = h/4",
+           "steps": K}
+    for on in (False, True):
+        sim = sph.create(sc, stream=stream)
+        if on:
+            out["corners"] = int(np.prod(sim.enable_voxels(0.5 * h, h, 0.25 * h)))
+        sim.step_profiled(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = sim.step_profiled(K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        out["with_voxels" if on else "without"] = {"ms_per_step": 1e3 * wall / K,
+                                                    "density_phase_us": 1e3 * ph["density"] / K}
+    us = 1e3 * (out["with_voxels"]["ms_per_step"] - out["without"]["ms_per_step"])
+    out["voxel_us_per_step"] = us
+    out["corners_per_s"] = out["corners"] / (us * 1e-6) if us > 0 else None
+    log(f"[bench] voxel: {out['corners']} corners, {us:.1f} us per field")
+    return out
+
+
 def batched_leg(sph, scenes, torch, args):
     """512 independent dam breaks of uneven size: one batched context vs a loop of plain steps."""
     scs = scenes.batched(args.scenes)
@@ -306,6 +337,8 @@ def main():
     ap.add_argument("--search", action="store_true", help="add the list-based neighbour-search comparison")
     ap.add_argument("--search-steps", type=int, default=100)
     ap.add_argument("--search-mode", type=int, default=0, help="neighbour search of --plain-steps (0, 1, 2)")
+    ap.add_argument("--voxel", action="store_true", help="add the voxel-density comparison")
+    ap.add_argument("--voxel-plain", action="store_true", help="--plain-steps with the voxel field on")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the HBM "
                          "byte counters of a profiler against a kernel of known traffic) and exit")
@@ -345,6 +378,9 @@ def main():
             sim.set_tuning(*[int(t) for t in args.tuning.split(",")])
         if args.search_mode:
             sim.set_search(args.search_mode)
+        if args.voxel_plain:
+            h = sc.params["h"]
+            sim.enable_voxels(0.5 * h, h, 0.25 * h)
         sim.step(args.plain_steps)
         torch.cuda.synchronize()
         log(f"[bench] {args.plain_steps} plain steps done, tuning {sim.tuning()}")
@@ -460,6 +496,8 @@ def main():
         result["closure"] = closure_leg(sph, scenes, torch, args)
     if args.search:
         result["search"] = search_leg(sph, scenes, torch, args)
+    if args.voxel:
+        result["voxel"] = voxel_leg(sph, scenes, torch, args)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)

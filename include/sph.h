@@ -102,8 +102,9 @@ typedef enum {
      entries are sorted indices and every list includes the particle itself */
   SPH_NBR_LIST_COUNTS = 21,  /* uint32 [n]: entries of each particle's list */
   SPH_NBR_LIST_OFFSETS = 22, /* uint32 [n + 1]: first entry of each list (sorted list only) */
-  SPH_NBR_LIST = 23          /* uint32 [list capacity]: the list buffer (bucket list: 27 x capacity
+  SPH_NBR_LIST = 23,         /* uint32 [list capacity]: the list buffer (bucket list: 27 x capacity
                                 entries per particle, the first SPH_NBR_LIST_COUNTS of them valid) */
+  SPH_VOXEL_FIELD = 24       /* float32 [nz][ny][nx]: voxel density at the cube corners (sph_voxel_enable) */
 } sph_field;
 
 typedef struct sph_info {
@@ -202,6 +203,22 @@ const char* sph_variant_name(int32_t fused, int32_t variant);
    capacity were left out, never written out of bounds).  Drops a captured
    graph.  Synchronises the stream. */
 sph_status sph_search_set(sph_ctx* ctx, int32_t mode, int32_t bucket_capacity, int32_t list_per_particle);
+
+/* Voxel density at cube corners ("Voxel Density" section).  At corner
+   x_c = box_min + c * spacing (per axis fl32(box_min + fl32(c * spacing)),
+   c = 0 .. floor((box_max - box_min) / spacing), x fastest),
+     phi(x) = |x - xbar| - r,  xbar = sum_i w_i x_i,
+     w_i = k(|x - x_i| / R) / sum_j k(|x - x_j| / R),  k(s) = (1 - s^2)^3,
+   over the particles with fl32 |x - x_i|^2 < fl32(R^2); a corner with none
+   has phi = +inf.  Every particle has radius r (particle_radius), so the
+   paper's weighted mean radius is r.  Once enabled, each step computes the
+   field of the state it starts from (the positions its density pass uses),
+   readable as SPH_VOXEL_FIELD; before the first step it holds zeros.
+   spacing <= 0 turns the field off.  dims (may be NULL) receives the corners
+   per axis (0 when off).  Single-scene contexts only (SPH_ENOTIMPL
+   otherwise); at most 2^31 corners (SPH_ECAPACITY).  Runs the step as one
+   launch per phase.  Drops a captured graph.  Synchronises the stream. */
+sph_status sph_voxel_enable(sph_ctx* ctx, float spacing, float radius, float particle_radius, int32_t* dims);
 
 /* ---------------------------------------------------------------------------
    Learned coupling closure.  A small MLP (256 -> 128 -> 128 -> 3, GELU after

@@ -28,7 +28,7 @@ CLOSURE_PARAMS, CLOSURE_FEATURES = 49795, 256
 POS, VEL, AGENT_POS, AGENT_VEL, DENSITY, NBR_COUNT, CELL_KEY, ACC_INT, ACC_COUPLE, TOUCHED, \
     AGENT_FORCE, AGENT_STEER, AGENT_COUNTS, SORTED_IDS, CELL_OFFSETS, AGENT_KEY, AGENT_SORTED_IDS, \
     AGENT_CELL_OFFSETS, PAIR_COUNT, AGENT_FEATURES, AGENT_FORCE_MODEL, NBR_LIST_COUNTS, NBR_LIST_OFFSETS, \
-    NBR_LIST = range(24)
+    NBR_LIST, VOXEL_FIELD = range(25)
 # neighbour search of the fluid passes (sph_search_set)
 SEARCH_TILES, SEARCH_SORTED_LIST, SEARCH_BUCKET_LIST = 0, 1, 2
 
@@ -40,7 +40,7 @@ _FIELD_DTYPE = {
     CELL_OFFSETS: (np.uint32, 1), AGENT_KEY: (np.uint32, 1), AGENT_SORTED_IDS: (np.uint32, 1),
     AGENT_CELL_OFFSETS: (np.uint32, 1), PAIR_COUNT: (np.uint64, 1), AGENT_FEATURES: (np.uint16, 256),
     AGENT_FORCE_MODEL: (np.float32, 3), NBR_LIST_COUNTS: (np.uint32, 1), NBR_LIST_OFFSETS: (np.uint32, 1),
-    NBR_LIST: (np.uint32, 1),
+    NBR_LIST: (np.uint32, 1), VOXEL_FIELD: (np.float32, 1),
 }
 
 
@@ -154,6 +154,8 @@ def lib() -> ctypes.CDLL:
         L.sph_tuning_get.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.sph_variant_count.restype = i32
         L.sph_variant_count.argtypes = [i32]
+        L.sph_voxel_enable.restype = ctypes.c_int
+        L.sph_voxel_enable.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.POINTER(i32)]
         L.sph_search_set.restype = ctypes.c_int
         L.sph_search_set.argtypes = [vp, i32, i32, i32]
         L.sph_variant_name.restype = ctypes.c_char_p
@@ -305,6 +307,15 @@ class Simulation:
     def set_search(self, mode: int, bucket_capacity: int = 0, list_per_particle: int = 0) -> None:
         """Neighbour search of the fluid passes: SEARCH_TILES, SEARCH_SORTED_LIST or SEARCH_BUCKET_LIST."""
         _check(lib().sph_search_set(self._ctx, int(mode), int(bucket_capacity), int(list_per_particle)), self._ctx)
+
+    def enable_voxels(self, spacing: float, radius: float, particle_radius: float):
+        """Voxel density at cube corners from the next step on; returns the corners per axis (x, y, z).
+        spacing <= 0 turns it off."""
+        dims = (ctypes.c_int32 * 3)()
+        _check(lib().sph_voxel_enable(self._ctx, float(spacing), float(radius), float(particle_radius), dims),
+               self._ctx)
+        self.voxel_dims = tuple(dims)
+        return self.voxel_dims
 
     def tuning(self) -> Dict:
         t = Tuning()

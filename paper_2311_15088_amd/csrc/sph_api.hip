@@ -527,8 +527,8 @@ sph_status sph_ctx_closure_buffers(sph_ctx* ctx) {
 static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 
 sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
-  // the closure, feature collection and the list forms run per-phase launches
-  if (ctx->fused && !ctx->closure && !ctx->features && ctx->list.mode == kSearchTiles) {
+  // the closure, feature collection, the list forms and the voxel field run per-phase launches
+  if (ctx->fused && !ctx->closure && !ctx->features && ctx->list.mode == kSearchTiles && !ctx->voxel.phi) {
     FusedPlan F;
     F.sort = ctx->sort;
     F.phys = ctx->phys;
@@ -558,6 +558,7 @@ static void launch_phase(sph_ctx* ctx, int p, hipStream_t st, hipEvent_t start, 
   } else if (p == kSortPhases) {
     if (lists) launch_list_density(ctx->phys, ctx->list, st, start, stop);
     else launch_density(ctx->phys, st, start, stop);
+    launch_voxel(ctx->phys, ctx->voxel, st);
   } else if (p == kSortPhases + 1) {
     sph_ctx_closure_phase(ctx, st);
     launch_agents(ctx->phys, st);
@@ -779,6 +780,7 @@ int64_t field_bytes(const sph_ctx* ctx, int32_t f) {
     case SPH_NBR_LIST_COUNTS: return 4 * N;
     case SPH_NBR_LIST_OFFSETS: return 4 * (N + 1);
     case SPH_NBR_LIST: return 4 * (int64_t)ctx->list.list_cap;
+    case SPH_VOXEL_FIELD: return 4 * (int64_t)ctx->voxel.n;
     default: return -1;
   }
 }
@@ -799,6 +801,8 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
     return fail(ctx, SPH_ESTATE, "no neighbour lists: the search mode is the tiled gather");
   if (field == SPH_NBR_LIST_OFFSETS && ctx->list.mode != kSearchSortedList)
     return fail(ctx, SPH_ESTATE, "list offsets exist for the sorted list only (bucket list: 27 x capacity per particle)");
+  if (field == SPH_VOXEL_FIELD && !ctx->voxel.phi)
+    return fail(ctx, SPH_ESTATE, "the voxel field is off (sph_voxel_enable)");
   if (need == 0) return SPH_OK;
   hipStream_t st = ctx->stream;
   if (!ctx->staging || ctx->staging_bytes < (size_t)need) {
@@ -883,6 +887,9 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
       break;
     case SPH_NBR_LIST:
       HIPCHK(hipMemcpyAsync(out, ctx->list.list, (size_t)need, hipMemcpyDeviceToDevice, st));
+      break;
+    case SPH_VOXEL_FIELD:
+      HIPCHK(hipMemcpyAsync(out, ctx->voxel.phi, (size_t)need, hipMemcpyDeviceToDevice, st));
       break;
   }
   HIPCHK(hipGetLastError());
@@ -1234,6 +1241,7 @@ void sph_destroy(sph_ctx* ctx) {
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->cl_arena) (void)hipFree(ctx->cl_arena);
   if (ctx->list_arena) (void)hipFree(ctx->list_arena);
+  if (ctx->voxel.phi) (void)hipFree(ctx->voxel.phi);
   delete ctx;
 }
 
@@ -1311,6 +1319,56 @@ sph_status sph_search_set(sph_ctx* ctx, int32_t mode, int32_t bucket_capacity, i
   L.ncells = (uint32_t)cells;
   ctx->list = L;
   ctx->list_arena = arena;
+  return SPH_OK;
+}
+
+sph_status sph_voxel_enable(sph_ctx* ctx, float spacing, float radius, float particle_radius, int32_t* dims) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  if (ctx->nscenes != 1) return fail(ctx, SPH_ENOTIMPL, "the voxel field is computed for single-scene contexts");
+  const bool on = spacing > 0.0f;
+  if (on && !(std::isfinite(spacing) && radius > 0.0f && std::isfinite(radius) && particle_radius >= 0.0f &&
+              std::isfinite(particle_radius)))
+    return fail(ctx, SPH_EINVAL, "need spacing > 0, radius > 0 and particle_radius >= 0, all finite");
+  const sph_params& p = ctx->params[0];
+  int d[3] = {0, 0, 0};
+  uint64_t n = 0;
+  if (on) {
+    n = 1;
+    for (int k = 0; k < 3; ++k) {
+      const double c = std::floor(((double)p.box_max[k] - (double)p.box_min[k]) / (double)spacing) + 1.0;
+      if (!(c >= 1.0) || c > 1.0e9) return fail(ctx, SPH_ECAPACITY, "too many corners along axis %d", k);
+      d[k] = (int)c;
+      n *= (uint64_t)d[k];
+    }
+    if (n > (1ull << 31)) return fail(ctx, SPH_ECAPACITY, "%llu corners: at most 2^31", (unsigned long long)n);
+  }
+  sph_status st = drop_graph(ctx);
+  if (st != SPH_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));  // earlier steps may still write the old field
+  if (ctx->voxel.phi) HIPCHK(hipFree(ctx->voxel.phi));
+  ctx->voxel = VoxelPlan{};
+  if (dims) dims[0] = d[0], dims[1] = d[1], dims[2] = d[2];
+  if (!on) return SPH_OK;
+  VoxelPlan V{};
+  hipError_t e = hipMalloc((void**)&V.phi, 4 * (size_t)n);
+  if (e != hipSuccess) return fail(ctx, SPH_ENOMEM, "voxel field: %s", hipGetErrorString(e));
+  e = hipMemsetAsync(V.phi, 0, 4 * (size_t)n, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(V.phi);
+    return fail(ctx, SPH_EHIP, "voxel field: %s", hipGetErrorString(e));
+  }
+  V.n = (uint32_t)n;
+  for (int k = 0; k < 3; ++k) {
+    V.dims[k] = d[k];
+    V.mn[k] = p.box_min[k];
+  }
+  V.gs = spacing;
+  V.R2 = (float)((double)radius * (double)radius);
+  V.inv_R2 = (float)(1.0 / (double)V.R2);
+  V.r = particle_radius;
+  V.reach = (float)((double)radius * (1.0 + 1e-3));
+  ctx->voxel = V;
   return SPH_OK;
 }
 

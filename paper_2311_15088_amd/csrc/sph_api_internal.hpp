@@ -82,6 +82,9 @@ struct sph_ctx {
   // neighbour-list forms of the fluid passes (mode kSearchTiles: none)
   sph::ListPlan list{};
   char* list_arena = nullptr;
+
+  // voxel density at cube corners (phi == nullptr: off)
+  sph::VoxelPlan voxel{};
 };
 
 sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vector<int64_t>& n,

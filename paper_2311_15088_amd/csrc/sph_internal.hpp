@@ -120,6 +120,19 @@ void launch_list_density(const PhysPlan& P, const ListPlan& L, hipStream_t st, h
 void launch_list_force(const PhysPlan& P, const ListPlan& L, hipStream_t st, hipEvent_t start = nullptr,
                        hipEvent_t stop = nullptr);
 
+// Voxel density at cube corners (single-scene contexts): the field of the
+// state a step starts from, computed after its density pass.
+struct VoxelPlan {
+  float* phi;          // [n] corner values, x fastest (nullptr: off)
+  uint32_t n;          // corners
+  int dims[3];         // corners per axis
+  float mn[3], gs;     // corner c at fl(mn + fl(c gs)) per axis
+  float R2, inv_R2;    // R^2 (float32 of the double square), 1 / R^2
+  float r;             // particle radius
+  float reach;         // R with a margin for float32 rounding (cell ranges)
+};
+void launch_voxel(const PhysPlan& P, const VoxelPlan& V, hipStream_t st);
+
 // One persistent launch per step (all phases, grid-wide barriers).
 constexpr int kFusedBD = 256;
 struct FusedPlan {

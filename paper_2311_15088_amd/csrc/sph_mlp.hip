@@ -439,15 +439,20 @@ void launch_features(const PhysPlan& P, const ClosurePlan& C, bool always, hipSt
 
 // ------------------------------------------------------- fused inference --
 
-// One wave per 16 agents: the three layers in registers and a per-wave LDS
-// tile, on the same v_mfma_f32_16x16x32_bf16 sequence as k_gemm (operand k
-// order, k steps of 32 in ascending order, the same epilogues), so fhat is
-// bit-identical to mlp_forward followed by the scaling.  A lane's A fragment
-// is row (lane % 16), k 8 (lane / 16) .. + 7 of the step; its B fragment the
-// same k of column (lane % 16) of the tile, read from the transposed weights
-// as 16 contiguous bytes; the result holds rows 4 (lane / 16) + q, column
-// lane % 16.
+// One wave per kInferTiles 16-row tiles of agents: the three layers in
+// registers and a per-wave LDS tile, on the same v_mfma_f32_16x16x32_bf16
+// sequence as k_gemm (operand k order, k steps of 32 in ascending order, the
+// same epilogues), so fhat is bit-identical to mlp_forward followed by the
+// scaling.  Each weight fragment loaded is used for every row tile of the
+// wave.  (Four tiles per wave took 336 registers, one wave per SIMD, and ran
+// slower: 79 us against 61 us at 65,536 agents, where the exact GELU
+// epilogues are most of the vector work.)  A lane's A fragment is row (lane % 16) of a tile, k
+// 8 (lane / 16) .. + 7 of the step; its B fragment the same k of column
+// (lane % 16), read from the transposed weights as 16 contiguous bytes; the
+// result holds rows 4 (lane / 16) + q, column lane % 16.
 constexpr int kInferWaves = 4;
+constexpr int kInferTiles = 1;                   // 16-row tiles per wave
+constexpr int kInferRows = 16 * kInferTiles;     // agents per wave
 constexpr int kHPad = kHid + 8;  // LDS row of a hidden tile (16-byte aligned rows)
 
 // LDS written by some lanes of a wave and read by others: order them
@@ -465,68 +470,98 @@ __global__ void __launch_bounds__(kInferWaves * kWave) k_closure_infer(const uin
                                                                      const uint16_t* __restrict__ wt,
                                                                      const float* __restrict__ w, ClosurePlan C,
                                                                      float scale) {
-  __shared__ __attribute__((aligned(16))) uint16_t sH[kInferWaves][16][kHPad];
+  constexpr int T = kInferTiles, NJ = kHid / 16;
+  __shared__ __attribute__((aligned(16))) uint16_t sH[kInferWaves][kInferRows][kHPad];
   if (!C.state[kClNeed]) return;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const uint32_t r0 = (blockIdx.x * kInferWaves + wave) * 16u;
+  const uint32_t r0 = (blockIdx.x * kInferWaves + wave) * (uint32_t)kInferRows;
   if (r0 >= rows) return;  // whole wave; no block-wide barriers below
   const int fr = lane & 15, fk = (lane >> 4) * 8, qr = (lane >> 4) * 4;
-  const uint32_t ra = r0 + (uint32_t)fr;  // the row this lane feeds
   uint16_t(*H)[kHPad] = sH[wave];
+  const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
 
   // layer 1: H1 = bf16(gelu(X W1 + b1))
-  f32x4 acc[kHid / 16];
+  f32x4 acc[NJ][T];
 #pragma unroll
-  for (int j = 0; j < kHid / 16; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < kFeat; k0 += 32) {
-    bf16x8 a = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-    if (ra < rows) a = ld_frag(X + (size_t)ra * kFeat + k0 + fk);
+    bf16x8 a[T];
 #pragma unroll
-    for (int j = 0; j < kHid / 16; ++j)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld_frag(wt + kOffT1 + (j * 16 + fr) * kFeat + k0 + fk),
-                                                        acc[j], 0, 0, 0);
+    for (int t = 0; t < T; ++t) {
+      const uint32_t ra = r0 + (uint32_t)(16 * t + fr);
+      a[t] = ra < rows ? ld_frag(X + (size_t)ra * kFeat + k0 + fk) : zero;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const bf16x8 bj = ld_frag(wt + kOffT1 + (j * 16 + fr) * kFeat + k0 + fk);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bj, acc[j][t], 0, 0, 0);
+    }
   }
 #pragma unroll
-  for (int j = 0; j < kHid / 16; ++j)
+  for (int j = 0; j < NJ; ++j) {
+    const float bias = w[kOffB1 + j * 16 + fr];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) H[qr + q][j * 16 + fr] = f2bf(gelu(acc[j][q] + w[kOffB1 + j * 16 + fr]));
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) H[16 * t + qr + q][j * 16 + fr] = f2bf(gelu(acc[j][t][q] + bias));
+  }
   wave_lds_sync();
 
   // layer 2: H2 = bf16(gelu(H1 W2 + b2)), written over H1 once it has been read
 #pragma unroll
-  for (int j = 0; j < kHid / 16; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < NJ; ++j)
 #pragma unroll
+    for (int t = 0; t < T; ++t) acc[j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < kHid; k0 += 32) {
-    const bf16x8 a = ld_frag(&H[fr][k0 + fk]);
+    bf16x8 a[T];
 #pragma unroll
-    for (int j = 0; j < kHid / 16; ++j)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, ld_frag(wt + kOffT2 + (j * 16 + fr) * kHid + k0 + fk),
-                                                        acc[j], 0, 0, 0);
+    for (int t = 0; t < T; ++t) a[t] = ld_frag(&H[16 * t + fr][k0 + fk]);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const bf16x8 bj = ld_frag(wt + kOffT2 + (j * 16 + fr) * kHid + k0 + fk);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bj, acc[j][t], 0, 0, 0);
+    }
   }
   wave_lds_sync();  // every lane has read H1
 #pragma unroll
-  for (int j = 0; j < kHid / 16; ++j)
+  for (int j = 0; j < NJ; ++j) {
+    const float bias = w[kOffB2 + j * 16 + fr];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) H[qr + q][j * 16 + fr] = f2bf(gelu(acc[j][q] + w[kOffB2 + j * 16 + fr]));
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) H[16 * t + qr + q][j * 16 + fr] = f2bf(gelu(acc[j][t][q] + bias));
+  }
   wave_lds_sync();
 
   // layer 3: y = H2 W3 + b3 (columns 3..15 of the tile are zero weights)
-  f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 y[T];
 #pragma unroll
-  for (int k0 = 0; k0 < kHid; k0 += 32)
-    y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld_frag(&H[fr][k0 + fk]), ld_frag(wt + kOffT3 + fr * kHid + k0 + fk), y,
-                                                0, 0, 0);
-  if (fr >= kOut) return;
+  for (int t = 0; t < T; ++t) y[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t a = r0 + (uint32_t)(qr + q);
-    if (a < rows) C.fhat[3 * (size_t)a + fr] = C.occ[a] ? (y[q] + w[kOffB3 + fr]) * scale : 0.0f;
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const bf16x8 b3 = ld_frag(wt + kOffT3 + fr * kHid + k0 + fk);
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      y[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld_frag(&H[16 * t + fr][k0 + fk]), b3, y[t], 0, 0, 0);
   }
+  if (fr >= kOut) return;
+  const float bias = w[kOffB3 + fr];
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t a = r0 + (uint32_t)(16 * t + qr + q);
+      if (a < rows) C.fhat[3 * (size_t)a + fr] = C.occ[a] ? (y[t][q] + bias) * scale : 0.0f;
+    }
 }
 
 void launch_closure_infer(const MlpWeights& W, const ClosurePlan& C, uint32_t na, hipStream_t st) {
   if (!na) return;
-  const uint32_t per_block = kInferWaves * 16u;
+  const uint32_t per_block = kInferWaves * (uint32_t)kInferRows;
   hipLaunchKernelGGL(k_closure_infer, dim3((na + per_block - 1) / per_block), dim3(kInferWaves * kWave), 0, st,
                      C.feat, na, W.wt, W.w, C, W.scale);
 }

@@ -1,0 +1,112 @@
+"""Voxel density at cube corners (sph_voxel_enable) against the oracle
+(oracle/voxel.py): which corners have particles within R bit-exactly, phi
+within 1e-4 R, on small scenes in full and on the 1M-particle workload sampled."""
+import numpy as np
+import pytest
+
+import paper_2311_15088_amd as sph
+from oracle import voxel
+from paper_2311_15088_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _voxel_args(sc):
+    h = sc.params["h"]
+    return 0.5 * h, h, 0.25 * h  # corner spacing, neighbourhood radius R, particle radius r
+
+
+def _compare(got, want, R, sample=None):
+    if sample is not None:
+        got, want = got[sample], want[sample]
+    inf_g, inf_w = np.isinf(got), np.isinf(want)
+    np.testing.assert_array_equal(inf_g, inf_w)
+    assert (~inf_w).sum() > 0
+    err = np.max(np.abs(got[~inf_w].astype(np.float64) - want[~inf_w]))
+    print(f"[voxel] {len(got)} corners, {(~inf_w).sum()} inside, max |phi err| / R = {err / R:.2e}", flush=True)
+    assert err <= 1e-4 * R
+    return err
+
+
+def test_voxel_field_matches_oracle():
+    for sc in (scenes.small_dam(nx=13, ny=7, nz=11, n_agents=37, agents="inside"), scenes.config0c()):
+        gs, R, r = _voxel_args(sc)
+        sim = sph.create(sc)
+        dims = sim.enable_voxels(gs, R, r)
+        assert dims == voxel.corner_dims(sc.params, gs)
+        sim.step(1)
+        got = sim.read(sph.VOXEL_FIELD)
+        assert got.size == dims[0] * dims[1] * dims[2]
+        _compare(got, voxel.field(sc.params, sc.x, gs, R, r), R)
+        # two more steps: the field is that of the state the last step started from
+        sim.step(1)
+        x2 = sim.read(sph.POS)
+        sim.step(1)
+        _compare(sim.read(sph.VOXEL_FIELD), voxel.field(sc.params, x2, gs, R, r), R)
+        sim.close()
+
+
+def test_voxel_field_leaves_the_step_unchanged():
+    sc = scenes.config0c()
+    a = sph.create(sc)
+    a.enable_voxels(*_voxel_args(sc))
+    a.step(3)
+    b = sph.create(sc)
+    b.step(3)
+    for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL, sph.DENSITY):
+        np.testing.assert_array_equal(a.read(f), b.read(f))
+    a.close()
+    b.close()
+
+
+def test_voxel_config1_sampled():
+    sc = scenes.config1()
+    gs, R, r = _voxel_args(sc)
+    sim = sph.create(sc)
+    dims = sim.enable_voxels(gs, R, r)
+    sim.step(1)
+    got = sim.read(sph.VOXEL_FIELD)
+    n = dims[0] * dims[1] * dims[2]
+    rng = np.random.default_rng(11)
+    # corners near the fluid (phi finite) and elsewhere, plus the last corner
+    inside = np.nonzero(np.isfinite(got))[0]
+    sample = np.unique(np.concatenate([rng.choice(n, 1500, replace=False), rng.choice(inside, 1500, replace=False),
+                                       [0, n - 1]]))
+    want = voxel.field(sc.params, sc.x, gs, R, r, sample=sample)
+    _compare(got, want, R, sample)
+    sim.close()
+
+
+def test_voxel_edge_cases():
+    sc = scenes.small_dam()
+    sim = sph.create(sc)
+    with pytest.raises(sph.SphError) as e:
+        sim.read(sph.VOXEL_FIELD)
+    assert e.value.status == sph.ESTATE
+    for bad in ((0.01, 0.0, 0.0), (0.01, -1.0, 0.0), (0.01, 0.05, -1.0), (0.01, float("inf"), 0.0)):
+        with pytest.raises(sph.SphError) as e:
+            sim.enable_voxels(*bad)
+        assert e.value.status == sph.EINVAL
+    assert sim.enable_voxels(0.0, 0.05, 0.01) == (0, 0, 0)  # off
+    # a radius below the particle spacing: most corners have no particle -> +inf
+    dims = sim.enable_voxels(0.013, 0.004, 0.002)
+    sim.step(1)
+    got = sim.read(sph.VOXEL_FIELD)
+    _compare(got, voxel.field(sc.params, sc.x, 0.013, 0.004, 0.002), 0.004)
+    sim.close()
+    # no fluid at all: every corner is +inf
+    empty = scenes.small_dam()
+    empty.x = empty.x[:0]
+    empty.v = empty.v[:0]
+    sim = sph.create(empty)
+    sim.enable_voxels(0.05, 0.05, 0.01)
+    sim.step(1)
+    assert np.all(np.isinf(sim.read(sph.VOXEL_FIELD)))
+    sim.close()
+    # batched contexts: not supported
+    specs = scenes.batched_specs(2, n_range=(300, 600), a_range=(2, 4))
+    bat = sph.create_batch([scenes.batched_scene(sp, k) for k, sp in enumerate(specs)])
+    with pytest.raises(sph.SphError) as e:
+        bat.enable_voxels(0.05, 0.05, 0.01)
+    assert e.value.status == sph.ENOTIMPL
+    bat.close()

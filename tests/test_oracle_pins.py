@@ -448,3 +448,69 @@ def test_neighbour_lists_agree_with_brute_force_and_are_ordered():
         assert np.abs(d).max() <= 1
         rank = ((d[:, 2] + 1) * 3 + (d[:, 1] + 1)).astype(np.int64) * len(c) + lst
         assert np.all(np.diff(rank) > 0)
+
+
+# ---- voxel density at cube corners (oracle/voxel.py) ------------------------
+
+def _voxel_params():
+    return scenes.default_params(0.05, 5e-4, (0, 0, 0), (0.4, 0.3, 0.35))
+
+
+def test_voxel_single_particle_is_a_sphere():
+    """One particle: every weight is 1, so phi = |x - x_1| - r inside R, +inf outside."""
+    from oracle import voxel
+    p = _voxel_params()
+    x1 = np.array([[0.1234, 0.1567, 0.0891]], np.float32)
+    R, r = 0.05, 0.0125
+    phi = voxel.field(p, x1, 0.025, R, r)
+    q = voxel.corners(p, 0.025).astype(np.float64)
+    d = np.linalg.norm(q - x1.astype(np.float64), axis=1)
+    near = d < R * (1 - 1e-6)
+    far = d > R * (1 + 1e-6)
+    assert near.sum() > 20
+    np.testing.assert_allclose(phi[near], d[near] - np.float32(r), rtol=0, atol=1e-12)
+    assert np.all(np.isinf(phi[far]))
+    # corners per axis: floor(extent / spacing) + 1 on the float32 values;
+    # with dyadic values the count is exact
+    pd = scenes.default_params(0.05, 5e-4, (0, 0, 0), (13 / 32, 5 / 16, 11 / 32))
+    assert voxel.corner_dims(pd, 1 / 32) == (14, 11, 12)
+
+
+def test_voxel_symmetric_pair_centres_on_the_corner():
+    """Particles mirrored about a corner get equal weights: xbar is the corner, phi = -r."""
+    from oracle import voxel
+    p = _voxel_params()
+    q = voxel.corners(p, 0.025)
+    c = q[5 + 17 * (6 + 13 * 7)].astype(np.float64)  # an interior corner
+    off = np.array([0.011, -0.007, 0.004])
+    x = np.array([c + off, c - off, c + 3 * np.array([0.05, 0.0, 0.0])], np.float32)
+    # the mirrored pair is exact in float32 only if the corner and offsets are: use the rounded values
+    xbar_rounding = np.abs(x[0].astype(np.float64) + x[1].astype(np.float64) - 2 * c).max()
+    phi = voxel.field(p, x, 0.025, 0.05, 0.01)
+    got = phi[5 + 17 * (6 + 13 * 7)]
+    assert abs(got - (-np.float32(0.01))) <= xbar_rounding + 1e-12
+
+
+def test_voxel_tree_search_matches_brute_force_and_bounds():
+    """The k-d tree only narrows candidates: the same field as a plain loop over
+    all particles on a small random cloud; and |x - xbar| >= 0 gives phi >= -r."""
+    from oracle import voxel
+    p = _voxel_params()
+    rng = np.random.default_rng(3)
+    x = (rng.random((300, 3)) * np.array([0.4, 0.3, 0.35])).astype(np.float32)
+    R, r = 0.06, 0.01
+    phi = voxel.field(p, x, 0.05, R, r)
+    q = voxel.corners(p, 0.05)
+    r2 = np.float32(float(np.float32(R)) ** 2)
+    for c in range(q.shape[0]):
+        m = voxel.inside_f32(q[c], x, r2)
+        if not m.any():
+            assert np.isinf(phi[c])
+            continue
+        xi = x[m].astype(np.float64)
+        s2 = np.sum((q[c].astype(np.float64) - xi) ** 2, axis=1) / float(np.float32(R)) ** 2
+        k = (1 - s2) ** 3
+        xbar = (k[:, None] * xi).sum(0) / k.sum()
+        want = np.linalg.norm(q[c].astype(np.float64) - xbar) - float(np.float32(r))
+        assert abs(phi[c] - want) < 1e-12
+        assert phi[c] >= -float(np.float32(r)) - 1e-15
