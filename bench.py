@@ -218,6 +218,32 @@ def voxel_leg(sph, scenes, torch, args):
     return out
 
 
+def obstacle_leg(sph, scenes, torch, args):
+    """Obstacle avoidance on the 1M-particle workload: two boxes in the boids'
+    region (the agent phase with and without the obstacle term)."""
+    sc = scenes.config1()
+    lo, hi = sc.y.min(0), sc.y.max(0)
+    ext = hi - lo
+    boxes = np.array([np.concatenate([lo + 0.2 * ext, lo + 0.4 * ext]),
+                      np.concatenate([lo + 0.6 * ext, lo + 0.8 * ext])], np.float32)
+    stream = torch.cuda.current_stream().cuda_stream
+    K = args.search_steps
+    out = {"workload": "dam break 1,048,576 particles + 1,024 boids, two boxes among the boids, vertices every h",
+           "steps": K}
+    for on in (False, True):
+        sim = sph.create(sc, stream=stream)
+        if on:
+            sim.set_obstacles(boxes, sc.params["h"], 1.0)
+        sim.step_profiled(10)
+        torch.cuda.synchronize()
+        ph = sim.step_profiled(K)
+        torch.cuda.synchronize()
+        sim.close()
+        out["with_obstacles_agents_us" if on else "without_agents_us"] = 1e3 * ph["agents"] / K
+    log(f"[bench] obstacles: agents phase {out['without_agents_us']:.2f} -> {out['with_obstacles_agents_us']:.2f} us")
+    return out
+
+
 def batched_leg(sph, scenes, torch, args):
     """512 independent dam breaks of uneven size: one batched context vs a loop of plain steps."""
     scs = scenes.batched(args.scenes)
@@ -338,6 +364,7 @@ def main():
     ap.add_argument("--search-steps", type=int, default=100)
     ap.add_argument("--search-mode", type=int, default=0, help="neighbour search of --plain-steps (0, 1, 2)")
     ap.add_argument("--voxel", action="store_true", help="add the voxel-density comparison")
+    ap.add_argument("--obstacles", action="store_true", help="add the obstacle-avoidance comparison")
     ap.add_argument("--voxel-plain", action="store_true", help="--plain-steps with the voxel field on")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (calibrates the HBM "
@@ -498,6 +525,8 @@ def main():
         result["search"] = search_leg(sph, scenes, torch, args)
     if args.voxel:
         result["voxel"] = voxel_leg(sph, scenes, torch, args)
+    if args.obstacles:
+        result["obstacles"] = obstacle_leg(sph, scenes, torch, args)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)

@@ -220,6 +220,23 @@ sph_status sph_search_set(sph_ctx* ctx, int32_t mode, int32_t bucket_capacity, i
    launch per phase.  Drops a captured graph.  Synchronises the stream. */
 sph_status sph_voxel_enable(sph_ctx* ctx, float spacing, float radius, float particle_radius, int32_t* dims);
 
+/* Obstacle Grid and obstacle avoidance ("Underwater Agent Behaviors" and
+   "Boid Motion and Agent Fluid Interaction" sections).  boxes[n_boxes][6]
+   (min x, y, z, max x, y, z; host memory) are axis-aligned obstacles.  A box's
+   mesh is its six faces, each a lattice of (n_u + 1) x (n_v + 1) vertices,
+   n = max(1, ceil(extent / vertex_spacing)), at min + ((max - min) i) / n in
+   double rounded to float, each carrying the face's outward normal.  Each
+   vertex goes to the agent-grid cell of its position; a cell's obstacle normal
+   is the mean of its vertices' normals.  Every step, a boid then adds
+     weight * sum over the 27 agent cells c around its own of omega_c n_c
+   to its steering, omega_c = 2 if the centre of c (min + (c + 1/2) d) is
+   within r_sep of the boid, 1 if within r_ali, else 0 (float32 squared
+   distances).  n_boxes = 0 removes the obstacles.  The grid is built on the
+   host here (obstacles are static); single-scene contexts only (SPH_ENOTIMPL
+   otherwise); at most 2^26 vertices (SPH_ECAPACITY).  Drops a captured graph.
+   Synchronises the stream. */
+sph_status sph_obstacles_set(sph_ctx* ctx, int32_t n_boxes, const float* boxes, float vertex_spacing, float weight);
+
 /* ---------------------------------------------------------------------------
    Learned coupling closure.  A small MLP (256 -> 128 -> 128 -> 3, GELU after
    the hidden layers; bfloat16 operands, float32 accumulation) maps an agent's

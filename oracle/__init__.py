@@ -75,6 +75,8 @@ def lib():
         L.orc_step.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_Out)]
+        L.orc_step_ex.restype = ctypes.c_int
+        L.orc_step_ex.argtypes = L.orc_step.argtypes[:-1] + [ctypes.c_void_p, ctypes.POINTER(_Out)]
         L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -118,13 +120,15 @@ def _c(a, dt):
 
 
 def step(p: Dict, x, v, y, u, fsample: Optional[np.ndarray] = None, asample: Optional[np.ndarray] = None,
-         nbr_mode: int = 0) -> Dict[str, np.ndarray]:
+         nbr_mode: int = 0, agent_acc: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """One reference time step from the float32 state (id order).
 
     Returns a dict of numpy arrays: cell keys, counts, offsets, sorted ids,
     neighbour counts, density, internal / coupling acceleration, new fluid
     state, agent keys and order, agent neighbour counts, steering, coupling
-    force and new agent state.  Entries outside ``fsample`` / ``asample`` are
+    force and new agent state.  ``agent_acc`` ([na, 3], id order) is a further
+    steering acceleration added to the boid rules (obstacle avoidance,
+    ``oracle/obstacles.py``).  Entries outside ``fsample`` / ``asample`` are
     NaN (or 0xFFFFFFFF for counts).
     """
     x = _c(x, np.float32).reshape(-1, 3)
@@ -148,10 +152,11 @@ def step(p: Dict, x, v, y, u, fsample: Optional[np.ndarray] = None, asample: Opt
         setattr(out, name, r[name].ctypes.data_as(typ))
     fs = None if fsample is None else _c(fsample, np.int64)
     as_ = None if asample is None else _c(asample, np.int64)
-    rc = lib().orc_step(ctypes.byref(_params(p, nbr_mode)), n, x.ctypes.data, v.ctypes.data, na, y.ctypes.data,
-                        u.ctypes.data, None if fs is None else fs.ctypes.data, 0 if fs is None else fs.size,
-                        None if as_ is None else as_.ctypes.data, 0 if as_ is None else as_.size,
-                        ctypes.byref(out))
+    acc = None if agent_acc is None else _c(agent_acc, np.float64).reshape(na, 3)
+    rc = lib().orc_step_ex(ctypes.byref(_params(p, nbr_mode)), n, x.ctypes.data, v.ctypes.data, na, y.ctypes.data,
+                           u.ctypes.data, None if fs is None else fs.ctypes.data, 0 if fs is None else fs.size,
+                           None if as_ is None else as_.ctypes.data, 0 if as_ is None else as_.size,
+                           None if acc is None else acc.ctypes.data, ctypes.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected the input")
     return r

@@ -318,6 +318,12 @@ static void fill_ones(uint32_t* a, int64_t m) {
 int orc_step(const orc_params* p, int64_t n, const float* x, const float* v, int64_t na, const float* y,
              const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
              orc_out* out) {
+  return orc_step_ex(p, n, x, v, na, y, u, fsample, n_fs, asample, n_as, NULL, out);
+}
+
+int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, int64_t na, const float* y,
+                const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
+                const double* agent_acc, orc_out* out) {
   if (n < 0 || na < 0 || (n > 0 && (!x || !v)) || (na > 0 && (!y || !u))) return -1;
   grid_t g, ga;
   if (make_grid(p, 0, &g) || make_grid(p, 1, &ga)) return -1;
@@ -502,6 +508,9 @@ int orc_step(const orc_params* p, int64_t n, const float* x, const float* v, int
       double st[3];
       for (int k = 0; k < 3; ++k)
         st[k] = (double)(float)p->w_sep * sep[k] + (double)(float)p->w_ali * ali[k] + (double)(float)p->w_coh * coh[k];
+      /* further steering given per agent (obstacle avoidance), added to the rules */
+      if (agent_acc)
+        for (int k = 0; k < 3; ++k) st[k] += agent_acc[3 * a + k];
       /* coupling force on the agent: F_a = sum_j G_aj over fluid within r_couple */
       find(&ff, ya, c.rc2_32, ns_c, -1, &kb);
       double F[3] = {0, 0, 0};

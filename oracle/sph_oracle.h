@@ -61,6 +61,12 @@ int orc_step(const orc_params* p, int64_t n, const float* x, const float* v, int
              const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
              orc_out* out);
 
+/* orc_step with a further steering acceleration per agent (agent_acc[na][3],
+   id order, may be NULL), added to the boid rules before the integration. */
+int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, int64_t na, const float* y,
+                const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
+                const double* agent_acc, orc_out* out);
+
 /* Number of OpenMP threads the oracle runs with. */
 int orc_threads(void);
 

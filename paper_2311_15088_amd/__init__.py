@@ -156,6 +156,8 @@ def lib() -> ctypes.CDLL:
         L.sph_variant_count.argtypes = [i32]
         L.sph_voxel_enable.restype = ctypes.c_int
         L.sph_voxel_enable.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.POINTER(i32)]
+        L.sph_obstacles_set.restype = ctypes.c_int
+        L.sph_obstacles_set.argtypes = [vp, i32, vp, ctypes.c_float, ctypes.c_float]
         L.sph_search_set.restype = ctypes.c_int
         L.sph_search_set.argtypes = [vp, i32, i32, i32]
         L.sph_variant_name.restype = ctypes.c_char_p
@@ -307,6 +309,12 @@ class Simulation:
     def set_search(self, mode: int, bucket_capacity: int = 0, list_per_particle: int = 0) -> None:
         """Neighbour search of the fluid passes: SEARCH_TILES, SEARCH_SORTED_LIST or SEARCH_BUCKET_LIST."""
         _check(lib().sph_search_set(self._ctx, int(mode), int(bucket_capacity), int(list_per_particle)), self._ctx)
+
+    def set_obstacles(self, boxes, vertex_spacing: float, weight: float) -> None:
+        """Axis-aligned obstacle boxes [n, 6] (min xyz, max xyz); an empty list removes them."""
+        b = np.ascontiguousarray(np.asarray(boxes, np.float32).reshape(-1, 6))
+        _check(lib().sph_obstacles_set(self._ctx, int(b.shape[0]), b.ctypes.data if b.size else None,
+                                       float(vertex_spacing), float(weight)), self._ctx)
 
     def enable_voxels(self, spacing: float, radius: float, particle_radius: float):
         """Voxel density at cube corners from the next step on; returns the corners per axis (x, y, z).

@@ -225,6 +225,35 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
     }
   }
 
+  // --- obstacle avoidance: lane q < 27 takes obstacle cell q of the 27 around
+  // the agent's cell; a cell counts twice if its centre is within r_sep, once
+  // if within r_ali ("Boid Motion" section, obstacle avoidance) ---
+  float ob[3] = {0.0f, 0.0f, 0.0f};
+  if (P.obst) {
+    if (lane < 27) {
+      const int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
+      if (x >= 0 && x < S.ga.dim[0] && y >= 0 && y < S.ga.dim[1] && z >= 0 && z < S.ga.dim[2]) {
+        const float4 o = P.obst[S.acbase + hash3(S.ga, x, y, z)];
+        if (o.w > 0.0f) {
+          float c[3];
+          {
+#pragma clang fp contract(off)
+            c[0] = S.ga.mn[0] + ((float)x + 0.5f) * S.ga.cell;
+            c[1] = S.ga.mn[1] + ((float)y + 0.5f) * S.ga.cell;
+            c[2] = S.ga.mn[2] + ((float)z + 0.5f) * S.ga.cell;
+          }
+          const float d2 = dist2_exact(c[0] - ya[0], c[1] - ya[1], c[2] - ya[2]);
+          const float om = d2 < S.rsep2 ? 2.0f : (d2 < S.rali2 ? 1.0f : 0.0f);
+          ob[0] = om * o.x;
+          ob[1] = om * o.y;
+          ob[2] = om * o.z;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ob[k] = wave_sum_f(ob[k]);
+  }
+
   // --- wave reductions (fixed order: deterministic) ---
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -260,6 +289,7 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     steer[k] = S.wsep * sep[k] + S.wali * dv[k] * ia + S.wcoh * dp[k] * ic;
+    if (P.obst) steer[k] += P.obst_w * ob[k];
     un[k] = ua[k] + S.dt * (steer[k] + S.cf * F[k] * S.inv_m);
   }
   const float sp = sqrtf(un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);

@@ -1242,6 +1242,7 @@ void sph_destroy(sph_ctx* ctx) {
   if (ctx->cl_arena) (void)hipFree(ctx->cl_arena);
   if (ctx->list_arena) (void)hipFree(ctx->list_arena);
   if (ctx->voxel.phi) (void)hipFree(ctx->voxel.phi);
+  if (ctx->obst) (void)hipFree(ctx->obst);
   delete ctx;
 }
 
@@ -1319,6 +1320,80 @@ sph_status sph_search_set(sph_ctx* ctx, int32_t mode, int32_t bucket_capacity, i
   L.ncells = (uint32_t)cells;
   ctx->list = L;
   ctx->list_arena = arena;
+  return SPH_OK;
+}
+
+// get_cell on one axis in float32 (the device's cell_coord, on the host)
+static int host_cell(float p, float mn, float inv, int dim) {
+#pragma clang fp contract(off)
+  float t = p - mn;
+  t = t * inv;
+  const float f = floorf(t);
+  if (!(f >= 0.0f)) return 0;
+  if (f >= (float)dim) return dim - 1;
+  return (int)f;
+}
+
+sph_status sph_obstacles_set(sph_ctx* ctx, int32_t n_boxes, const float* boxes, float vertex_spacing,
+                             float weight) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  if (ctx->nscenes != 1) return fail(ctx, SPH_ENOTIMPL, "obstacles are set for single-scene contexts");
+  if (n_boxes < 0 || (n_boxes > 0 && !boxes)) return fail(ctx, SPH_EINVAL, "n_boxes < 0 or NULL boxes");
+  if (n_boxes > 0 && !(vertex_spacing > 0.0f && std::isfinite(vertex_spacing) && std::isfinite(weight)))
+    return fail(ctx, SPH_EINVAL, "need vertex_spacing > 0 and a finite weight");
+  // the mesh of each box: its six faces, each a lattice of vertices with the
+  // face's outward normal; summed per agent-grid cell in double
+  const DGrid& ga = ctx->hs[0].ga;
+  std::vector<double> sum(4 * (size_t)ga.ncells, 0.0);  // nx, ny, nz, count
+  uint64_t verts = 0;
+  for (int b = 0; b < n_boxes; ++b) {
+    const float* bx = boxes + 6 * (size_t)b;
+    for (int k = 0; k < 6; ++k)
+      if (!std::isfinite(bx[k])) return fail(ctx, SPH_EINVAL, "box %d is not finite", b);
+    for (int k = 0; k < 3; ++k)
+      if (!(bx[k] <= bx[3 + k])) return fail(ctx, SPH_EINVAL, "box %d has min > max on axis %d", b, k);
+    for (int k = 0; k < 3; ++k) {
+      const int u = k == 0 ? 1 : 0, v = k == 2 ? 1 : 2;
+      const double lu = bx[u], hu = bx[3 + u], lv = bx[v], hv = bx[3 + v];
+      const double nu = std::max(1.0, std::ceil((hu - lu) / (double)vertex_spacing));
+      const double nv = std::max(1.0, std::ceil((hv - lv) / (double)vertex_spacing));
+      verts += 2 * (uint64_t)(nu + 1) * (uint64_t)(nv + 1);
+      if (verts > (1ull << 26)) return fail(ctx, SPH_ECAPACITY, "more than 2^26 obstacle vertices");
+      for (int side = 0; side < 2; ++side) {
+        const float fk = side ? bx[3 + k] : bx[k];
+        for (int j = 0; j <= (int)nv; ++j)
+          for (int i = 0; i <= (int)nu; ++i) {
+            float q[3];
+            q[k] = fk;
+            q[u] = (float)(lu + ((hu - lu) * i) / nu);
+            q[v] = (float)(lv + ((hv - lv) * j) / nv);
+            int c[3];
+            for (int a = 0; a < 3; ++a) c[a] = host_cell(q[a], ga.mn[a], ga.inv, ga.dim[a]);
+            const size_t key = (size_t)c[0] + (size_t)ga.dim[0] * ((size_t)c[1] + (size_t)ga.dim[1] * c[2]);
+            sum[4 * key + k] += side ? 1.0 : -1.0;
+            sum[4 * key + 3] += 1.0;
+          }
+      }
+    }
+  }
+  sph_status st = drop_graph(ctx);
+  if (st != SPH_OK) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));  // earlier steps may still read the old grid
+  if (ctx->obst) HIPCHK(hipFree(ctx->obst));
+  ctx->obst = nullptr;
+  ctx->phys.obst = nullptr;
+  ctx->phys.obst_w = 0.0f;
+  if (n_boxes == 0) return SPH_OK;
+  std::vector<float4> h((size_t)ga.ncells);
+  for (size_t c = 0; c < h.size(); ++c) {
+    const double n = sum[4 * c + 3];
+    h[c] = n > 0.0 ? make_float4((float)(sum[4 * c] / n), (float)(sum[4 * c + 1] / n), (float)(sum[4 * c + 2] / n), 1.0f)
+                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  HIPCHK(hipMalloc((void**)&ctx->obst, sizeof(float4) * h.size()));
+  HIPCHK(hipMemcpy(ctx->obst, h.data(), sizeof(float4) * h.size(), hipMemcpyHostToDevice));
+  ctx->phys.obst = ctx->obst;
+  ctx->phys.obst_w = weight;
   return SPH_OK;
 }
 

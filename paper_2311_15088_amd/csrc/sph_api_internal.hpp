@@ -85,6 +85,9 @@ struct sph_ctx {
 
   // voxel density at cube corners (phi == nullptr: off)
   sph::VoxelPlan voxel{};
+
+  // obstacle grid (phys.obst; owned here)
+  float4* obst = nullptr;
 };
 
 sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vector<int64_t>& n,

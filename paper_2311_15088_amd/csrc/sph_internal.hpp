@@ -67,6 +67,10 @@ struct PhysPlan {
   const float* cl_fhat;
   const uint32_t* cl_state;
   float* cl_err;
+  // obstacle grid on the agent grid (nullptr = no obstacles): per cell the
+  // mean normal of the obstacle-mesh vertices in it, w = 1 if it has any
+  const float4* obst;
+  float obst_w;                // weight of the avoidance steering
   // diagnostics (nullptr = off)
   float *d_aint, *d_acoup, *d_steer, *d_force;  // [n][3] / [a][3]
   uint32_t *d_touch, *d_acnt;                   // [n] / [a][4]

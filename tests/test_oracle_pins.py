@@ -514,3 +514,46 @@ def test_voxel_tree_search_matches_brute_force_and_bounds():
         want = np.linalg.norm(q[c].astype(np.float64) - xbar) - float(np.float32(r))
         assert abs(phi[c] - want) < 1e-12
         assert phi[c] >= -float(np.float32(r)) - 1e-15
+
+
+# ---- obstacle grid and avoidance (oracle/obstacles.py) ----------------------
+
+def _obstacle_case():
+    p = scenes.default_params(0.05, 5e-4, (0, 0, 0), (1.6, 1.6, 1.6))  # agent cells of 0.2002 (8 per axis)
+    box = [[0.3, 0.3, 0.3, 1.1, 1.1, 1.1]]  # faces in cells 1 and 5 of each axis
+    return p, box
+
+
+def test_obstacle_grid_face_cells():
+    """Cells crossed by the interior of one face hold only that face's vertices:
+    their mean normal is the face normal exactly; cells inside the box hold none;
+    the vertex count is (n + 1)^2 per face."""
+    from oracle import obstacles
+    p, box = _obstacle_case()
+    mean, cnt = obstacles.obstacle_grid(p, box, 0.05)
+    pts, nrm = obstacles.mesh_vertices(box, 0.05)
+    assert len(pts) == 6 * 17 * 17 and cnt.sum() == len(pts)
+    key = lambda cx, cy, cz: cx + 8 * (cy + 8 * cz)  # noqa: E731
+    for a in (2, 3, 4):
+        for b in (2, 3, 4):
+            np.testing.assert_array_equal(mean[key(a, b, 5)], [0, 0, 1])
+            np.testing.assert_array_equal(mean[key(a, b, 1)], [0, 0, -1])
+            np.testing.assert_array_equal(mean[key(5, a, b)], [1, 0, 0])
+            np.testing.assert_array_equal(mean[key(a, 1, b)], [0, -1, 0])
+            for c in (2, 3, 4):
+                assert cnt[key(a, b, c)] == 0
+
+
+def test_obstacle_avoidance_hand_cases():
+    """A boid above the +z face: its own cell (centre within r_sep) counts twice,
+    a face cell whose centre is within r_ali once, cells farther not at all."""
+    from oracle import obstacles
+    p, box = _obstacle_case()
+    d = np.float32(0.2001953125)
+    centre = np.float32(0) + (np.float32(3.5)) * d  # centre of cells 3 along x and y
+    cz = np.float32(0) + np.float32(5.5) * d
+    y = np.array([[centre, centre, cz],            # own cell centre: 2 x (0, 0, 1)
+                  [centre + 0.09, centre, cz],      # own 0.09 (x2), x-neighbour 0.110 (x1)
+                  [centre, centre, centre]], np.float32)  # box centre: cells 2..4 hold nothing
+    acc = obstacles.avoidance(p, y, box, 0.05, 1.5)
+    np.testing.assert_allclose(acc, [[0, 0, 3.0], [0, 0, 4.5], [0, 0, 0]], atol=1e-12)
