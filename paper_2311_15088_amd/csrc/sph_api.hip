@@ -436,6 +436,9 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   memset(&P, 0, sizeof P);
   P.scenes = ctx->d_scenes;
   P.nscenes = S;
+  P.unit_h = 1;
+  for (int s = 0; s < S; ++s)
+    if (!(hs[s].h2 <= 1.0f)) P.unit_h = 0;
   P.fprefix = ctx->d_fprefix;
   P.nf = ctx->N;
   P.aprefix = ctx->d_aprefix;

@@ -52,6 +52,7 @@ struct PhysPlan {
   uint32_t ntiles;
   int tx;                      // cells per tile along x (<= kTXMax)
   int variant;                 // kernel variant (block size, particles per thread, LDS capacity)
+  int unit_h;                  // every scene has h^2 <= 1 (a density-pass form relies on it)
   unsigned long long* tile_list;  // [cells] work items of this step (tile << 16 | first cell << 8 | last cell)
   uint32_t item_max;           // particles per work item before a tile is cut
   uint32_t* counters;          // [kWorkCounters]

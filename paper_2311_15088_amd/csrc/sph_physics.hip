@@ -20,9 +20,9 @@ __global__ void __launch_bounds__(256) k_fixup_tiles(const SortSet* __restrict__
   else fixup_block(sets, nsets, bprefix, blockIdx.x - tile_blocks);
 }
 
-template <bool FORCE, int BD, int CAP>
+template <bool FORCE, int BD, int CAP, bool UNIT_H = false>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
-  fluid_tiles<FORCE, BD, CAP>(P);
+  fluid_tiles<FORCE, BD, CAP, UNIT_H>(P);
 }
 
 template <int BD>
@@ -38,6 +38,7 @@ __global__ void __launch_bounds__(BD) k_agents(PhysPlan P) {
 // results (the candidate order of each particle does not depend on them).
 struct FluidVariant {
   const void* density;
+  const void* density_unit;  // the density pass when every scene has h^2 <= 1
   const void* force;
   int bd_density, bd_force, item_max;
   const char* name;
@@ -45,8 +46,8 @@ struct FluidVariant {
 
 template <int BDD, int CD, int BDF, int CF>
 static FluidVariant make_variant(int item_max, const char* name) {
-  return FluidVariant{(const void*)k_fluid<false, BDD, CD>, (const void*)k_fluid<true, BDF, CF>, BDD, BDF, item_max,
-                      name};
+  return FluidVariant{(const void*)k_fluid<false, BDD, CD>, (const void*)k_fluid<false, BDD, CD, true>,
+                      (const void*)k_fluid<true, BDF, CF>, BDD, BDF, item_max, name};
 }
 
 static const FluidVariant* variants() {
@@ -92,12 +93,13 @@ static int persistent_blocks(const void* fn, int bd) {
 // start / stop (may be null): events recorded when the kernel itself starts
 // and ends (hipExtLaunchKernel), without the gaps between launches.
 static void launch_fluid(const PhysPlan& P, bool force, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
-  static int grids[kNumVariants][2];
+  static int grids[kNumVariants][3];
   const int v = (P.variant >= 0 && P.variant < kNumVariants) ? P.variant : 0;
   const FluidVariant& V = variants()[v];
-  const void* fn = force ? V.force : V.density;
+  const int form = force ? 2 : (P.unit_h ? 1 : 0);
+  const void* fn = force ? V.force : (P.unit_h ? V.density_unit : V.density);
   const int bd = force ? V.bd_force : V.bd_density;
-  int& grid = grids[v][force ? 1 : 0];
+  int& grid = grids[v][form];
   if (!grid) grid = persistent_blocks(fn, bd);
   const uint32_t g = std::min<uint32_t>((uint32_t)grid, P.ntiles);
   void* args[] = {(void*)&P};
