@@ -1,6 +1,7 @@
 // sph_mlp.hip -- the learned coupling closure on the GPU: per-agent features,
 // a bfloat16 MFMA GEMM with fused epilogues, the MLP forward / backward passes,
-// Adam, and the per-step closure controller kernels.
+// Adam, the network of a step in one MFMA kernel, and the per-step closure
+// controller kernels.
 //
 // GEMM: a 256-thread workgroup computes a 64 x 64 tile of C as 2 x 2
 // wavefronts of 32 x 32, each a 2 x 2 grid of v_mfma_f32_16x16x32_bf16.  Every
@@ -43,8 +44,7 @@ constexpr int kGPad = 40; // LDS row length (elements)
 
 // AVEC: A has contiguous k and 16-byte aligned rows, staged 8 elements at a time
 template <int EPI, bool AVEC>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g, const uint32_t* gate) {
-  if (gate && !*gate) return;
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[kGT][kGPad];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[kGT][kGPad];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -132,24 +132,24 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, const uint32_t* gate) 
 }
 
 template <bool AVEC>
-static void gemm_v(const GemmArgs& g, int epi, const uint32_t* gate, hipStream_t st) {
+static void gemm_v(const GemmArgs& g, int epi, hipStream_t st) {
   const dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT);
   switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_gemm<kEpiStore, AVEC>), grid, dim3(256), 0, st, g, gate); break;
-    case kEpiBias: hipLaunchKernelGGL((k_gemm<kEpiBias, AVEC>), grid, dim3(256), 0, st, g, gate); break;
-    case kEpiBiasGelu: hipLaunchKernelGGL((k_gemm<kEpiBiasGelu, AVEC>), grid, dim3(256), 0, st, g, gate); break;
-    default: hipLaunchKernelGGL((k_gemm<kEpiGeluBwd, AVEC>), grid, dim3(256), 0, st, g, gate); break;
+    case kEpiStore: hipLaunchKernelGGL((k_gemm<kEpiStore, AVEC>), grid, dim3(256), 0, st, g); break;
+    case kEpiBias: hipLaunchKernelGGL((k_gemm<kEpiBias, AVEC>), grid, dim3(256), 0, st, g); break;
+    case kEpiBiasGelu: hipLaunchKernelGGL((k_gemm<kEpiBiasGelu, AVEC>), grid, dim3(256), 0, st, g); break;
+    default: hipLaunchKernelGGL((k_gemm<kEpiGeluBwd, AVEC>), grid, dim3(256), 0, st, g); break;
   }
 }
 
-static void gemm(const GemmArgs& g, int epi, const uint32_t* gate, hipStream_t st) {
+static void gemm(const GemmArgs& g, int epi, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return;
   const bool avec = g.sak == 1 && (g.sam & 7) == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
-  if (avec) gemm_v<true>(g, epi, gate, st);
-  else gemm_v<false>(g, epi, gate, st);
+  if (avec) gemm_v<true>(g, epi, st);
+  else gemm_v<false>(g, epi, st);
 }
 
-void launch_gemm(const GemmArgs& g, int epilogue, hipStream_t st) { gemm(g, epilogue, nullptr, st); }
+void launch_gemm(const GemmArgs& g, int epilogue, hipStream_t st) { gemm(g, epilogue, st); }
 
 static GemmArgs gargs(int M, int N, int K, const uint16_t* A, long long sam, long long sak, const uint16_t* B,
                       long long sbk, long long sbn) {
@@ -174,16 +174,16 @@ static void forward(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& w
   g.Z = wk.z1;
   g.Cb = wk.h1;
   g.bias = W.w + kOffB1;
-  gemm(g, kEpiBiasGelu, nullptr, st);
+  gemm(g, kEpiBiasGelu, st);
   g = gargs(rows, kHid, kHid, wk.h1, kHid, 1, W.wb + kOffW2, kHid, 1);
   g.Z = wk.z2;
   g.Cb = wk.h2;
   g.bias = W.w + kOffB2;
-  gemm(g, kEpiBiasGelu, nullptr, st);
+  gemm(g, kEpiBiasGelu, st);
   g = gargs(rows, kOut, kHid, wk.h2, kHid, 1, W.wb + kOffW3, kOut, 1);
   g.C = wk.y;
   g.bias = W.w + kOffB3;
-  gemm(g, kEpiBias, nullptr, st);
+  gemm(g, kEpiBias, st);
 }
 
 void mlp_forward(const MlpWeights& W, const uint16_t* x, int rows, MlpWork& wk, hipStream_t st) {
@@ -264,27 +264,27 @@ void mlp_backward_scaled(const MlpWeights& W, const uint16_t* x, const float* t,
   // layer 3: dW3 = H2^T dY, db3 = sum dY, dZ2 = (dY W3^T) * gelu'(Z2)
   GemmArgs g = gargs(kHid, kOut, rows, wk.h2, 1, kHid, wk.dyb, kOut, 1);
   g.C = W.grad + kOffW3;
-  gemm(g, kEpiStore, nullptr, st);
+  gemm(g, kEpiStore, st);
   colsum(wk.dy, rows, kOut, col, W.grad + kOffB3, st);
   g = gargs(rows, kHid, kOut, wk.dyb, kOut, 1, W.wb + kOffW3, 1, kOut);
   g.C = wk.dz2;
   g.Cb = wk.dz2b;
   g.aux = wk.z2;
-  gemm(g, kEpiGeluBwd, nullptr, st);
+  gemm(g, kEpiGeluBwd, st);
   // layer 2
   g = gargs(kHid, kHid, rows, wk.h1, 1, kHid, wk.dz2b, kHid, 1);
   g.C = W.grad + kOffW2;
-  gemm(g, kEpiStore, nullptr, st);
+  gemm(g, kEpiStore, st);
   colsum(wk.dz2, rows, kHid, col, W.grad + kOffB2, st);
   g = gargs(rows, kHid, kHid, wk.dz2b, kHid, 1, W.wb + kOffW2, 1, kHid);
   g.C = wk.dz1;
   g.Cb = wk.dz1b;
   g.aux = wk.z1;
-  gemm(g, kEpiGeluBwd, nullptr, st);
+  gemm(g, kEpiGeluBwd, st);
   // layer 1
   g = gargs(kFeat, kHid, rows, x, 1, kFeat, wk.dz1b, kHid, 1);
   g.C = W.grad + kOffW1;
-  gemm(g, kEpiStore, nullptr, st);
+  gemm(g, kEpiStore, st);
   colsum(wk.dz1, rows, kHid, col, W.grad + kOffB1, st);
 }
 
