@@ -1446,6 +1446,11 @@ sph_status sph_voxel_enable(sph_ctx* ctx, float spacing, float radius, float par
   V.inv_R2 = (float)(1.0 / (double)V.R2);
   V.r = particle_radius;
   V.reach = (float)((double)radius * (1.0 + 1e-3));
+  // cell rows a 64 x 2 x 2 block of corners can reach: per axis a span of one
+  // corner spacing plus 2 reach touches at most floor(span / cell) + 2 cells
+  // (one more allowed for rounding)
+  const double rows_axis = std::floor(((double)spacing + 2.0 * V.reach) / (double)ctx->hs[0].g.cell) + 3.0;
+  V.tile_ok = rows_axis * rows_axis <= 64.0 && d[1] <= 2 * 65535 && d[2] <= 2 * 65535;
   ctx->voxel = V;
   return SPH_OK;
 }

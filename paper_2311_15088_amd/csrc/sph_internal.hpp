@@ -135,6 +135,7 @@ struct VoxelPlan {
   float R2, inv_R2;    // R^2 (float32 of the double square), 1 / R^2
   float r;             // particle radius
   float reach;         // R with a margin for float32 rounding (cell ranges)
+  int tile_ok;         // a 64 x 2 x 2 corner block reaches at most 64 cell rows
 };
 void launch_voxel(const PhysPlan& P, const VoxelPlan& V, hipStream_t st);
 
