@@ -4,10 +4,12 @@
 // and rbar = r (every particle has radius r).  A corner with no particle
 // within R gets +inf.
 //
-// A second neighbour gather on the step's cell table.  k_voxel runs one
-// thread per corner, corners in x-fastest order, reading the particles from
-// HBM through the caches; k_voxel_rows (below, the form launched when the
-// grid fits a 3-D launch) stages them in LDS per segment of a corner row.  The sums are taken
+// A second neighbour gather on the step's cell table, in three forms that
+// give the same field: k_voxel_tile (64 x 2 x 2 corner blocks sharing their
+// LDS-staged cell rows; launched whenever a block's cell rows fit the table
+// of row spans), k_voxel_rows (one corner-row segment per workgroup; grids of
+// up to 65,535 corners in y and z) and k_voxel (one thread per corner reading
+// the particles through the caches; any grid).  The sums are taken
 // relative to the corner, sum k (x_i - x) and sum k, so |x - xbar| =
 // |sum k (x_i - x)| / sum k without cancellation.
 #include "sph_internal.hpp"
