@@ -966,6 +966,7 @@ static sph_status snapshot(sph_ctx* ctx, Snapshot& sn, bool save) {
       sn.parts.push_back({ctx->d_steer, 12 * A});
       sn.parts.push_back({ctx->d_acnt, 16 * A});
     }
+    if (ctx->voxel.phi) sn.parts.push_back({ctx->voxel.phi, 4 * (size_t)ctx->voxel.n});
     if (ctx->cl_arena) {
       sn.parts.push_back({ctx->cplan.feat, 2 * (size_t)kFeat * A});
       sn.parts.push_back({ctx->cplan.fhat, 12 * A});

@@ -55,6 +55,10 @@ def test_voxel_field_leaves_the_step_unchanged():
     b.step(3)
     for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL, sph.DENSITY):
         np.testing.assert_array_equal(a.read(f), b.read(f))
+    # the autotuner's trial steps leave the field (like every readable field) as it was
+    phi = a.read(sph.VOXEL_FIELD)
+    a.autotune(1)
+    np.testing.assert_array_equal(a.read(sph.VOXEL_FIELD), phi)
     a.close()
     b.close()
 
