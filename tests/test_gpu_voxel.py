@@ -46,6 +46,18 @@ def test_voxel_field_matches_oracle():
         sim.close()
 
 
+def test_voxel_wide_radius():
+    """R = 3 h: a 64 x 2 x 2 corner block would reach more cell rows than the
+    block form's table holds, so the corner-row form computes the field."""
+    sc = scenes.small_dam(nx=13, ny=7, nz=11, n_agents=5, agents="inside")
+    h = sc.params["h"]
+    sim = sph.create(sc)
+    sim.enable_voxels(0.5 * h, 3.0 * h, 0.25 * h)
+    sim.step(1)
+    _compare(sim.read(sph.VOXEL_FIELD), voxel.field(sc.params, sc.x, 0.5 * h, 3.0 * h, 0.25 * h), 3.0 * h)
+    sim.close()
+
+
 def test_voxel_field_leaves_the_step_unchanged():
     sc = scenes.config0c()
     a = sph.create(sc)
