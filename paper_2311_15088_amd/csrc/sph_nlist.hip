@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kListBD) k_bucket_fill(PhysPlan P, ListPlan L)
   const uint32_t c = S.cbase + hash3(S.g, cx, cy, cz);
   const uint32_t slot = atomicAdd(&L.bcnt[c], 1u);
   if (slot < L.cap) L.bucket[(size_t)c * L.cap + slot] = i;
-  else L.status[kBucketOverflow] = 1u;
+  else atomicOr(&L.status[kBucketOverflow], 1u);
 }
 
 // list[i][0 .. lcnt[i]) from the 27 buckets around the particle, cells in

@@ -143,3 +143,24 @@ def test_capacities_and_invalid_use():
         sim.read(sph.NBR_LIST_COUNTS)
     assert e.value.status == sph.ESTATE
     sim.close()
+
+
+def test_list_forms_dense_clump():
+    """Cells of about 200 particles and lists of hundreds of entries: the default
+    capacities are too small (flagged), larger ones give the tiled results."""
+    sc = scenes.clumped_dam()
+    ref = _run(sc, 2, sph.SEARCH_TILES)
+    for mode, kw in ((sph.SEARCH_SORTED_LIST, {}), (sph.SEARCH_BUCKET_LIST, {})):
+        sim = sph.create(sc)
+        sim.set_search(mode, **kw)
+        with pytest.raises(sph.SphError) as e:
+            sim.step(1)
+        assert e.value.status == sph.ECAPACITY
+        sim.close()
+    got = _run(sc, 2, sph.SEARCH_SORTED_LIST, list_per_particle=1024)
+    for f in EXACT:
+        np.testing.assert_array_equal(got[f], ref[f], err_msg=f"field {f}")
+    got = _run(sc, 2, sph.SEARCH_BUCKET_LIST, bucket_capacity=512)
+    for f in (sph.NBR_COUNT, sph.SORTED_IDS, sph.PAIR_COUNT):
+        np.testing.assert_array_equal(got[f], ref[f])
+    assert np.max(np.abs(got[sph.DENSITY] - ref[sph.DENSITY]) / ref[sph.DENSITY]) < 1e-5
