@@ -22,7 +22,7 @@ namespace sph {
 // order and the wave reductions run in a fixed order, so the results are
 // deterministic.
 // ----------------------------------------------------------------------------
-constexpr int kGatherBatch = 4;
+constexpr int kGatherBatch = 2;
 
 template <int BD>
 __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
