@@ -54,7 +54,7 @@ FLOP_FORCE_PER_PARTICLE = 30
 # runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scale factors a plain
 # 1 GiB device copy reads on the same counters), averaged over the 1,000 steps
 # this script times; valid only for the kernel sources it was measured on.
-TRAFFIC_FORCE = {"sources_sha256_16": "202bf95d776f86b3", "bytes_per_launch": 315.0e6,
+TRAFFIC_FORCE = {"sources_sha256_16": "202bf95d776f86b3", "bytes_per_launch": 315.4e6,
                  "measured_on": "the 1,000 timed steps"}
 FORCE_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
 
