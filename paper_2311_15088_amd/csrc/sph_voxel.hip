@@ -228,9 +228,27 @@ __global__ void __launch_bounds__(kVoxelBD) k_voxel_tile(PhysPlan P, VoxelPlan V
       const uint32_t rb = uniform_u32(staged ? s_rb[r] : off[hash3(S.g, bhi[0], y, z) + 1]);
       if (ra >= rb) continue;
       // this corner's part of the row (none if the row is outside its y / z range)
-      const bool mine = act && y >= tlo[1] && y <= thi[1] && z >= tlo[2] && z <= thi[2];
-      const uint32_t ta = mine ? off[hash3(S.g, tlo[0], y, z)] : 0u;
-      const uint32_t tb = mine ? off[hash3(S.g, thi[0], y, z) + 1] : 0u;
+      bool mine = act && y >= tlo[1] && y <= thi[1] && z >= tlo[2] && z <= thi[2];
+      // the row's cells that the sphere of radius R around the corner meets:
+      // its distance to the row's y / z slab (less a margin of 1e-3 cells for
+      // the rounding of the cell bounds) leaves a half-width e along x
+      int x0 = tlo[0], x1 = thi[0];
+      if (mine) {
+        const float tol = 1e-3f * S.g.cell;
+        const float ylo = S.g.mn[1] + (float)y * S.g.cell, zlo = S.g.mn[2] + (float)z * S.g.cell;
+        const float dy = fmaxf(fmaxf(ylo - q[1], q[1] - (ylo + S.g.cell)) - tol, 0.0f);
+        const float dz = fmaxf(fmaxf(zlo - q[2], q[2] - (zlo + S.g.cell)) - tol, 0.0f);
+        const float e2 = V.reach * V.reach - (dy * dy + dz * dz);
+        if (e2 <= 0.0f) {
+          mine = false;
+        } else {
+          const float e = sqrtf(e2);
+          x0 = cell_coord(q[0] - e, S.g.mn[0], S.g.inv, S.g.dim[0]);
+          x1 = cell_coord(q[0] + e, S.g.mn[0], S.g.inv, S.g.dim[0]);
+        }
+      }
+      const uint32_t ta = mine ? off[hash3(S.g, x0, y, z)] : 0u;
+      const uint32_t tb = mine ? off[hash3(S.g, x1, y, z) + 1] : 0u;
       for (uint32_t c0 = ra; c0 < rb; c0 += kVoxelCap) {
         const uint32_t len = min((uint32_t)kVoxelCap, rb - c0);
         __syncthreads();
