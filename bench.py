@@ -18,6 +18,16 @@ Three regions run the same K steps from the same initial state:
   * graph region: K steps replayed from captured HIP graphs, without events
     (reported beside).
 
+`roofline` is that of the longer fluid pass of the timed region: its
+algorithmic bytes per launch (18 B per particle for density, 52 B for force +
+integration) over its average launch time, against 8 TB/s.  The force pass's
+figures against the FP32 vector ALU, which is what bounds it, are under `alu`.
+
+Then, unless left out: the 16.7M-particle scale workload (`scale`), 512
+batched scenes against plain per-scene loops (`batched`), the learned coupling
+closure against the exact gather on 4,194,304 particles and 65,536 agents
+(`closure`), and the CPU oracle on the host cores (`cpu_baseline`).
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -40,6 +50,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # dual issue) x 2.4 GHz.  This code is built without packed FP32, so half of
 # it (78.6 TFLOP/s) is the attainable ceiling; the published figure is the peak.
 PEAK_FP32_TFLOPS = 157.3
+ATTAINABLE_FP32_TFLOPS = 78.6
 
 # Algorithmic FP32 operations of the force + integration pass: per neighbour
 # pair (i, j in N_i) the pair term of the pressure and viscosity forces
@@ -50,23 +61,34 @@ PEAK_FP32_TFLOPS = 157.3
 FLOP_FORCE_PER_PAIR = 37
 FLOP_FORCE_PER_PARTICLE = 30
 
-# HBM traffic of one force + integration launch from two rocprofv3 counter
-# runs (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the scale factors a plain
-# 1 GiB device copy reads on the same counters), averaged over the 1,000 steps
-# this script times; valid only for the kernel sources it was measured on.
-TRAFFIC_FORCE = {"sources_sha256_16": "202bf95d776f86b3", "bytes_per_launch": 315.4e6,
-                 "measured_on": "the 1,000 timed steps"}
-FORCE_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
+# Algorithmic bytes per particle of the two fluid passes, each array counted
+# once per pass: density reads x (12) and writes rho (4) and the neighbour
+# count as 16 bits (2); force + integration reads x, v, rho (28) and writes
+# x', v' (24).
+B_ALG_PASS = {"density": 18, "force_integrate": 52}
+
+# HBM traffic per launch of the fluid passes from two rocprofv3 counter runs
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for a
+# plain device copy of known size), averaged over the timed steps of the run
+# named; valid only for the kernel sources it was measured on.
+TRAFFIC = {}
+FLUID_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
 
 
-def force_traffic():
+def sources_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in FORCE_SOURCES:
+    for f in FLUID_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_FORCE["bytes_per_launch"] if h.hexdigest()[:16] == TRAFFIC_FORCE["sources_sha256_16"] else None
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    t = TRAFFIC.get(kernel)
+    return t if t and t["sources_sha256_16"] == sources_hash() else None
+
 
 # Algorithmic bytes per element and launch for each kernel of a step (the
 # arrays each kernel must read and write once, in the layout it uses).
@@ -76,10 +98,10 @@ def force_traffic():
 #   scatter        reads key, rank, id (12), writes src, id (8)        per particle
 #   fixup_tile_list reads src, id, key (12), x, v (24), writes x, v, id (28) per particle
 #                  (the work-item list in the same launch: 8 per tile)
-#   density        reads x (12), writes rho, n (8)                     per particle
+#   density        reads x (12), writes rho (4), n (2)                 per particle
 #   force_integrate reads x, v, rho (28), writes x', v' (24)           per particle
 #   agents         reads y, u (24), writes y', u' (24)                 per agent
-B_PER_PARTICLE = {"key_count": 20, "scatter": 20, "fixup_tile_list": 64, "density": 20, "force_integrate": 52}
+B_PER_PARTICLE = {"key_count": 20, "scatter": 20, "fixup_tile_list": 64, "density": 18, "force_integrate": 52}
 B_PER_CELL = {"scan_reduce": 4, "scan_apply": 12}
 
 
@@ -97,6 +119,24 @@ def kernel_bytes(name, n, cells, agents):
     return 0
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy of `mib` MiB, timed with events: read + write bytes per second."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -107,27 +147,61 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(sc, budget_s: float):
-    """The CPU oracle timed on the host cores on whole steps of the same workload."""
-    import oracle  # test infrastructure: only this leg of the bench uses it
-
+def _oracle_rate(oracle, sc, budget_s, nbr_mode=1, max_steps=200):
+    """Whole oracle steps of a scene from its initial state until budget_s."""
     x, v, y, u = sc.x, sc.v, sc.y, sc.u
     steps = 0
     t0 = time.perf_counter()
     while True:
-        r = oracle.step(sc.params, x, v, y, u, nbr_mode=1)
+        r = oracle.step(sc.params, x, v, y, u, nbr_mode=nbr_mode)
         x, v = r["x1"].astype(np.float32), r["v1"].astype(np.float32)
         y, u = r["y1"].astype(np.float32), r["u1"].astype(np.float32)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 200:
-            break
-    return {
-        "value": steps * sc.n / el, "unit": "particle-steps/s", "cores": oracle.threads(), "kind": "oracle",
+        if el >= budget_s or steps >= max_steps:
+            return steps, el
+
+
+def cpu_baseline(sc, budget_s: float, full: bool):
+    """The CPU oracle timed on the host cores on whole steps of the same workload."""
+    import oracle  # test infrastructure: only this leg of the bench uses it
+    from paper_2311_15088_amd import scenes
+
+    threads = oracle.threads()
+    steps, el = _oracle_rate(oracle, sc, budget_s)
+    out = {
+        "value": steps * sc.n / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
         "sample": f"{steps} whole step(s) of the same {sc.n}-particle workload from its initial state, FP64 "
                   f"oracle with its cell-list neighbour finder (sets identical to brute force), "
-                  f"{oracle.threads()} OpenMP threads on '{cpu_model()}', {el:.1f} s",
+                  f"{threads} OpenMP threads on '{cpu_model()}' (nproc {os.cpu_count()}), {el:.1f} s",
     }
+    if full:
+        # the same on one core
+        oracle.set_threads(1)
+        s1, e1 = _oracle_rate(oracle, sc, 0.5 * budget_s)
+        out["one_core"] = {"value": s1 * sc.n / e1, "unit": "particle-steps/s", "cores": 1,
+                           "sample": f"{s1} whole step(s), {e1:.1f} s"}
+        oracle.set_threads(threads)
+        # brute force (the oracle's definition): config 0 for its 10 steps ...
+        c0 = scenes.config0()
+        s0, e0 = _oracle_rate(oracle, c0, 1e9, nbr_mode=0, max_steps=10)
+        out["brute_force_config0"] = {"value": s0 * c0.n / e0, "unit": "particle-steps/s", "cores": threads,
+                                      "sample": f"{s0} whole steps of the 4,096-particle scene, {e0:.2f} s"}
+        # ... and config 1 for one step on a sample of particles (every sampled
+        # particle and every neighbour whose density it needs is tested against
+        # all N particles)
+        rng = np.random.default_rng(5)
+        fs = np.sort(rng.choice(sc.n, 64, replace=False))
+        t0 = time.perf_counter()
+        r = oracle.step(sc.params, sc.x, sc.v, sc.y, sc.u, fsample=fs, asample=np.zeros(0, np.int64), nbr_mode=0)
+        eb = time.perf_counter() - t0
+        tested = int(len(fs) + r["nbr"][fs].sum())  # particles brute-forced (sample + density neighbours)
+        out["brute_force_config1"] = {
+            "particles_tested_per_s": tested / eb, "cores": threads,
+            "full_step_s_estimate": eb * sc.n / tested,
+            "sample": f"one step of 64 sampled particles of the same workload: {tested} particles tested "
+                      f"against all {sc.n} in {eb:.2f} s"}
+    return out
 
 
 def scale_leg(sph, scenes, torch, args):
@@ -245,42 +319,73 @@ def obstacle_leg(sph, scenes, torch, args):
 
 
 def batched_leg(sph, scenes, torch, args):
-    """512 independent dam breaks of uneven size: one batched context vs a loop of plain steps."""
+    """512 independent dam breaks of uneven size: one batched context (autotuned
+    form, K steps in one graph) against a loop over the scenes with one plain
+    context each, replayed from each scene's own graph of K steps, and against
+    the same loop launched eagerly."""
     scs = scenes.batched(args.scenes)
     n_tot = sum(s.n for s in scs)
     log(f"[bench] batched: {len(scs)} scenes, {n_tot} particles, {sum(s.n_agents for s in scs)} agents")
     stream = torch.cuda.current_stream().cuda_stream
-    bat = sph.create_batch(scs, stream=stream)
-    tuned = bat.autotune(2)
-    log(f"[bench] batched autotune: {tuned}")
     K = args.batched_steps
-    bat.step(2)
-    bat.capture(K)
-    torch.cuda.synchronize()
+    bat = sph.create_batch(scs, stream=stream)
     t0 = time.perf_counter()
-    bat.step(K)  # one graph of K steps
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    bat.close()
-    # a loop of plain steps, one scene after another (K_plain steps each)
-    Kp = max(1, K // 10)
-    tp = 0.0
-    for sc in scs:
-        sim = sph.create(sc, stream=stream)
-        sim.step(1)
+    tuned = bat.autotune(2)
+    t_tune = time.perf_counter() - t0
+    log(f"[bench] batched autotune ({t_tune:.1f} s): {tuned}")
+
+    def time_graph(sim):
+        sim.step(2)
+        sim.capture(K)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.step(Kp)
+        sim.step(K)  # one graph of K steps
         torch.cuda.synchronize()
-        tp += time.perf_counter() - t0
+        return time.perf_counter() - t0
+
+    tb = time_graph(bat)
+    # the persistent fused launch in its fastest variant, for the record
+    fused = {}
+    for v in range(sph.variant_count(1)):
+        bat.set_tuning(1, v, tuned["tile_x"])
+        fused[sph.variant_name(1, v)] = len(scs) * K / time_graph(bat)
+    bat.close()
+    # a loop of plain contexts, one per scene
+    sims = [sph.create(sc, stream=stream) for sc in scs]
+    for sim in sims:
+        sim.step(2)
+        sim.capture(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(K)  # each scene's own graph
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    for sim in sims:
+        sim.capture(0)
+    Ke = max(1, K // 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(Ke)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t0
+    for sim in sims:
         sim.close()
-    return {
+    rate = len(scs) * K / tb
+    out = {
+        "workload": f"{len(scs)} dam breaks, {n_tot} particles in total, N log-uniform in [2048, 262144]",
         "scenes": len(scs), "particles": n_tot, "steps": K,
-        "scene_steps_per_s": len(scs) * K / tb, "particle_steps_per_s": n_tot * K / tb,
-        "plain_loop_scene_steps_per_s": len(scs) * Kp / tp, "plain_loop_steps_per_scene": Kp,
-        "speedup_vs_plain_loop": (len(scs) * K / tb) / (len(scs) * Kp / tp),
-        "autotuned": tuned,
+        "scene_steps_per_s": rate, "particle_steps_per_s": n_tot * K / tb,
+        "autotuned": tuned, "autotune_s": t_tune, "fused_scene_steps_per_s": fused,
+        "plain_graph_loop_scene_steps_per_s": len(scs) * K / tg,
+        "plain_eager_loop_scene_steps_per_s": len(scs) * Ke / te, "plain_eager_loop_steps": Ke,
+        "speedup_vs_plain_graph_loop": rate / (len(scs) * K / tg),
+        "speedup_vs_plain_eager_loop": rate / (len(scs) * Ke / te),
     }
+    log(f"[bench] batched: {rate:.0f} scene-steps/s; plain graphs {out['plain_graph_loop_scene_steps_per_s']:.0f}, "
+        f"plain eager {out['plain_eager_loop_scene_steps_per_s']:.0f}")
+    return out
 
 
 def closure_leg(sph, scenes, torch, args):
@@ -350,16 +455,18 @@ def main():
     ap.add_argument("--chunk", type=int, default=50, help="steps per captured graph in the graph region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="add the one-core and brute-force timings of the CPU oracle")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--scale", action="store_true", help="add the 16.7M-particle scale workload")
-    ap.add_argument("--scale-steps", type=int, default=200)
-    ap.add_argument("--batched", action="store_true", help="add the batched-scenes comparison")
+    ap.add_argument("--no-scale", action="store_true", help="leave out the 16.7M-particle scale workload")
+    ap.add_argument("--scale-steps", type=int, default=50)
+    ap.add_argument("--no-batched", action="store_true", help="leave out the batched-scenes comparison")
     ap.add_argument("--scenes", type=int, default=512)
-    ap.add_argument("--batched-steps", type=int, default=100)
-    ap.add_argument("--closure", action="store_true", help="add the learned-closure comparison")
-    ap.add_argument("--pairs", type=int, default=2_000_000)
-    ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--closure-steps", type=int, default=1000)
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--no-closure", action="store_true", help="leave out the learned-closure comparison")
+    ap.add_argument("--pairs", type=int, default=262_144)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--closure-steps", type=int, default=100)
     ap.add_argument("--search", action="store_true", help="add the list-based neighbour-search comparison")
     ap.add_argument("--search-steps", type=int, default=100)
     ap.add_argument("--search-mode", type=int, default=0, help="neighbour search of --plain-steps (0, 1, 2)")
@@ -479,13 +586,16 @@ def main():
     # whole-step HBM fraction with B_alg = 154 + 24 C/N bytes per particle-step
     b_alg = 154.0 + 24.0 * cells / n
     hbm_frac_step = b_alg * n / (ms_per_step * 1e-3) / (PEAK_HBM_GBS * 1e9)
-    # roofline of the dominant kernel (force + integration): bound by vector
-    # ALU issue, not HBM (about 25 FP32 operations per byte it must move)
-    dom = "force_integrate"
+    # roofline of the dominant kernel of this run (the longer fluid pass):
+    # its algorithmic bytes per launch over its average launch duration
+    dom = max(("density", "force_integrate"), key=lambda k: kernel_ms[k])
     t_dom = kernel_ms[dom] / K * 1e-3
+    bytes_dom = B_ALG_PASS[dom] * n
+    ach = bytes_dom / t_dom / 1e9
+    tr = measured_traffic(dom)
+    # the force pass against the FP32 vector ALU, which is what bounds it
+    t_f = kernel_ms["force_integrate"] / K * 1e-3
     flop = (FLOP_FORCE_PER_PAIR * pairs / K + FLOP_FORCE_PER_PARTICLE * n)
-    ach = flop / t_dom / 1e12
-    ach_hbm = kernel_bytes(dom, n, cells, agents) / t_dom / 1e9
     result = {
         "metric": "particle-steps/s & %HBM roofline @1M SPH+boid; batched & surrogate vs plain",
         "value": value,
@@ -501,11 +611,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dam break 128x64x128 = 1,048,576 particles + 1,024 boids, h=0.02, dt=2e-4",
                    "n": n, "agents": agents, "cells": cells},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / PEAK_FP32_TFLOPS, "traffic": force_traffic(),
-                     "traffic_unit": "bytes per launch", "traffic_measured_on": TRAFFIC_FORCE["measured_on"],
-                     "flop_per_launch": flop, "us_per_launch": t_dom * 1e6,
-                     "hbm_alg_GBs": ach_hbm, "hbm_alg_frac": ach_hbm / PEAK_HBM_GBS},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM_GBS, "traffic": None if tr is None else tr["bytes_per_launch"],
+                     "traffic_unit": "bytes per launch", "traffic_measured_on": None if tr is None else tr["run"],
+                     "bytes_per_particle": B_ALG_PASS[dom], "particles_per_launch": n,
+                     "us_per_launch": t_dom * 1e6},
+        "alu": {"kernel": "force_integrate", "flop_per_launch": flop, "us_per_launch": t_f * 1e6,
+                "achieved_tflops": flop / t_f / 1e12, "peak_tflops": PEAK_FP32_TFLOPS,
+                "frac_of_peak": flop / t_f / 1e12 / PEAK_FP32_TFLOPS,
+                "frac_of_attainable": flop / t_f / 1e12 / ATTAINABLE_FP32_TFLOPS},
+        "kernels_hbm_frac": {k: B_ALG_PASS[k] * n / (kernel_ms[k] / K * 1e-3) / (PEAK_HBM_GBS * 1e9)
+                             for k in B_ALG_PASS},
         "step_hbm_frac": hbm_frac_step,
         "b_alg_bytes_per_particle_step": b_alg,
         "pair_interactions_per_s": pairs / wall,
@@ -514,12 +630,13 @@ def main():
         "phase_region": {"ms_per_step": phase_wall_ms,
                          "us_per_step": {k: 1e3 * vms / K for k, vms in phase_ms.items()}},
         "graph_ms_per_step": graph_ms,
+        "copy_kernel_GBs": copy_bandwidth(torch),
     }
-    if args.scale:
+    if not args.no_scale:
         result["scale"] = scale_leg(sph, scenes, torch, args)
-    if args.batched:
+    if not args.no_batched:
         result["batched"] = batched_leg(sph, scenes, torch, args)
-    if args.closure:
+    if not args.no_closure:
         result["closure"] = closure_leg(sph, scenes, torch, args)
     if args.search:
         result["search"] = search_leg(sph, scenes, torch, args)
@@ -529,7 +646,7 @@ def main():
         result["obstacles"] = obstacle_leg(sph, scenes, torch, args)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(sc, args.cpu_budget, args.cpu_full)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -137,12 +137,31 @@ sph_status sph_create_batch(const sph_params* per_scene, int32_t n_scenes, const
                             const float* agent_vel, void* hip_stream, sph_ctx** out);
 
 /* Advance n_steps >= 0 time steps (asynchronous).  Replays the captured
-   graph when one of n_steps steps exists (see sph_capture). */
+   graph when one of n_steps steps exists (see sph_capture).  Returns
+   SPH_EHIP, and enqueues nothing, once an earlier fused step is known to have
+   aborted (a grid barrier of the persistent step kernel timed out: the state
+   is then half-updated and every later fused launch leaves at once); the
+   knowledge arrives asynchronously, with the flag's copy that follows every
+   fused launch, so the call that enqueued the aborted step may still return
+   SPH_OK.  sph_read reports it without fail. */
 sph_status sph_step(sph_ctx* ctx, int32_t n_steps);
 
 /* Copy a field (sph_field) into dst (host or device), which must hold at
-   least the field's size in bytes; dst_bytes is checked. */
+   least the field's size in bytes; dst_bytes is checked.  A host dst
+   synchronises the stream; a device dst is enqueued, except on a context
+   that has run fused steps, where the call first waits for the stream and
+   returns SPH_EHIP (copying nothing) if any fused step aborted. */
 sph_status sph_read(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_bytes);
+
+/* Raise (raise != 0) or clear (raise == 0) the fused step's sticky abort
+   flag on the device, waiting for the stream first.  Raised, it acts like a
+   timed-out grid barrier: every later fused launch leaves at entry, without
+   touching the state, and sph_step / sph_read report SPH_EHIP.  Cleared, it
+   re-arms fused steps (and resets the barrier's arrival count); the caller
+   must restore a valid state itself (e.g. a fresh context from a saved one).
+   Lets a caller exercise its handling of that failure; per-phase launches
+   never read the flag. */
+sph_status sph_abort_set(sph_ctx* ctx, int32_t raise);
 
 /* Size in bytes of a field, or a negative status. */
 int64_t sph_field_bytes(const sph_ctx* ctx, int32_t field);

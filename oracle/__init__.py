@@ -57,6 +57,7 @@ class _Out(ctypes.Structure):
         ("akey", _U32P), ("n_sep", _U32P), ("n_ali", _U32P), ("n_coh", _U32P), ("n_cpl", _U32P),
         ("steer", _F64P), ("force", _F64P), ("y1", _F64P), ("u1", _F64P),
         ("acnt", _U32P), ("aoff", _U32P), ("asorted", _U32P),
+        ("x1f", _F64P), ("v1f", _F64P), ("y1f", _F64P), ("u1f", _F64P),
     ]
 
 
@@ -77,7 +78,11 @@ def lib():
                                ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_Out)]
         L.orc_step_ex.restype = ctypes.c_int
         L.orc_step_ex.argtypes = L.orc_step.argtypes[:-1] + [ctypes.c_void_p, ctypes.POINTER(_Out)]
+        L.orc_step_rho.restype = ctypes.c_int
+        L.orc_step_rho.argtypes = L.orc_step_ex.argtypes[:-1] + [ctypes.c_void_p, ctypes.POINTER(_Out)]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -115,20 +120,29 @@ def threads() -> int:
     return int(lib().orc_threads())
 
 
+def set_threads(n: int) -> None:
+    """Run the oracle on n OpenMP threads from now on."""
+    lib().orc_set_threads(int(n))
+
+
 def _c(a, dt):
     return np.ascontiguousarray(np.asarray(a, dtype=dt))
 
 
 def step(p: Dict, x, v, y, u, fsample: Optional[np.ndarray] = None, asample: Optional[np.ndarray] = None,
-         nbr_mode: int = 0, agent_acc: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+         nbr_mode: int = 0, agent_acc: Optional[np.ndarray] = None,
+         rho_in: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """One reference time step from the float32 state (id order).
 
     Returns a dict of numpy arrays: cell keys, counts, offsets, sorted ids,
     neighbour counts, density, internal / coupling acceleration, new fluid
     state, agent keys and order, agent neighbour counts, steering, coupling
-    force and new agent state.  ``agent_acc`` ([na, 3], id order) is a further
+    force and new agent state; ``x1f``, ``v1f``, ``y1f``, ``u1f`` are the new
+    states before the walls act.  ``agent_acc`` ([na, 3], id order) is a further
     steering acceleration added to the boid rules (obstacle avoidance,
-    ``oracle/obstacles.py``).  Entries outside ``fsample`` / ``asample`` are
+    ``oracle/obstacles.py``).  ``rho_in`` ([n], id order) replaces the
+    computed density in every force term (``rho`` still returns the computed
+    one).  Entries outside ``fsample`` / ``asample`` are
     NaN (or 0xFFFFFFFF for counts).
     """
     x = _c(x, np.float32).reshape(-1, 3)
@@ -146,6 +160,7 @@ def step(p: Dict, x, v, y, u, fsample: Optional[np.ndarray] = None, asample: Opt
         n_ali=np.zeros(na, np.uint32), n_coh=np.zeros(na, np.uint32), n_cpl=np.zeros(na, np.uint32),
         steer=np.zeros((na, 3)), force=np.zeros((na, 3)), y1=np.zeros((na, 3)), u1=np.zeros((na, 3)),
         acnt=np.zeros(nac, np.uint32), aoff=np.zeros(nac + 1, np.uint32), asorted=np.zeros(na, np.uint32),
+        x1f=np.zeros((n, 3)), v1f=np.zeros((n, 3)), y1f=np.zeros((na, 3)), u1f=np.zeros((na, 3)),
     )
     out = _Out()
     for name, typ in _Out._fields_:
@@ -153,10 +168,12 @@ def step(p: Dict, x, v, y, u, fsample: Optional[np.ndarray] = None, asample: Opt
     fs = None if fsample is None else _c(fsample, np.int64)
     as_ = None if asample is None else _c(asample, np.int64)
     acc = None if agent_acc is None else _c(agent_acc, np.float64).reshape(na, 3)
-    rc = lib().orc_step_ex(ctypes.byref(_params(p, nbr_mode)), n, x.ctypes.data, v.ctypes.data, na, y.ctypes.data,
-                           u.ctypes.data, None if fs is None else fs.ctypes.data, 0 if fs is None else fs.size,
-                           None if as_ is None else as_.ctypes.data, 0 if as_ is None else as_.size,
-                           None if acc is None else acc.ctypes.data, ctypes.byref(out))
+    rin = None if rho_in is None else _c(rho_in, np.float64).reshape(n)
+    rc = lib().orc_step_rho(ctypes.byref(_params(p, nbr_mode)), n, x.ctypes.data, v.ctypes.data, na, y.ctypes.data,
+                            u.ctypes.data, None if fs is None else fs.ctypes.data, 0 if fs is None else fs.size,
+                            None if as_ is None else as_.ctypes.data, 0 if as_ is None else as_.size,
+                            None if acc is None else acc.ctypes.data, None if rin is None else rin.ctypes.data,
+                            ctypes.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected the input")
     return r

@@ -27,6 +27,14 @@
 
 #define PI 3.14159265358979323846
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
@@ -324,6 +332,12 @@ int orc_step(const orc_params* p, int64_t n, const float* x, const float* v, int
 int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, int64_t na, const float* y,
                 const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
                 const double* agent_acc, orc_out* out) {
+  return orc_step_rho(p, n, x, v, na, y, u, fsample, n_fs, asample, n_as, agent_acc, NULL, out);
+}
+
+int orc_step_rho(const orc_params* p, int64_t n, const float* x, const float* v, int64_t na, const float* y,
+                 const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
+                 const double* agent_acc, const double* rho_in, orc_out* out) {
   if (n < 0 || na < 0 || (n > 0 && (!x || !v)) || (na > 0 && (!y || !u))) return -1;
   grid_t g, ga;
   if (make_grid(p, 0, &g) || make_grid(p, 1, &ga)) return -1;
@@ -393,6 +407,15 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
     }
     free(nb.v);
   }
+  /* densities given by the caller replace the computed ones in every force
+     term (the density output keeps the computed value) */
+  double* rho_own = NULL;
+  if (rho_in) {
+    rho_own = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    memcpy(rho_own, rho, sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+      if (need[i]) rho[i] = rho_in[i];
+  }
 
   /* ---- fluid outputs for the sample ---- */
   if (out) {
@@ -401,6 +424,8 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
     fill_nan(out->a_coup, 3 * n);
     fill_nan(out->x1, 3 * n);
     fill_nan(out->v1, 3 * n);
+    fill_nan(out->x1f, 3 * n);
+    fill_nan(out->v1f, 3 * n);
     fill_ones(out->nbr, n);
     fill_ones(out->touched, n);
   }
@@ -437,7 +462,7 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
         }
       }
       if (out) {
-        if (out->rho) out->rho[i] = rho[i];
+        if (out->rho) out->rho[i] = rho_own ? rho_own[i] : rho[i];
         if (out->nbr) out->nbr[i] = (uint32_t)nb.len;
         if (out->touched) out->touched[i] = (uint32_t)ab.len;
         double vn[3], xn[3];
@@ -446,6 +471,10 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
           if (out->a_coup) out->a_coup[3 * i + k] = ac[k];
           vn[k] = (double)vi[k] + dt * (acc[k] + ac[k] + gvec[k]);
           xn[k] = (double)xi[k] + dt * vn[k];
+        }
+        for (int k = 0; k < 3; ++k) {
+          if (out->x1f) out->x1f[3 * i + k] = xn[k];
+          if (out->v1f) out->v1f[3 * i + k] = vn[k];
         }
         walls(p, xn, vn);
         for (int k = 0; k < 3; ++k) {
@@ -464,6 +493,8 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
     fill_nan(out->force, 3 * na);
     fill_nan(out->y1, 3 * na);
     fill_nan(out->u1, 3 * na);
+    fill_nan(out->y1f, 3 * na);
+    fill_nan(out->u1f, 3 * na);
     fill_ones(out->n_sep, na);
     fill_ones(out->n_ali, na);
     fill_ones(out->n_coh, na);
@@ -533,6 +564,11 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
         for (int k = 0; k < 3; ++k) un[k] *= vmin / sp;
       }
       for (int k = 0; k < 3; ++k) yn[k] = (double)ya[k] + dt * un[k];
+      if (out)
+        for (int k = 0; k < 3; ++k) {
+          if (out->y1f) out->y1f[3 * a + k] = yn[k];
+          if (out->u1f) out->u1f[3 * a + k] = un[k];
+        }
       walls(p, yn, un);
       if (out) {
         if (out->n_sep) out->n_sep[a] = (uint32_t)sb.len;
@@ -573,5 +609,6 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
   free(asorted);
   free(need);
   free(rho);
+  free(rho_own);
   return 0;
 }

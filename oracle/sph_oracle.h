@@ -48,6 +48,9 @@ typedef struct {
   uint32_t *akey, *n_sep, *n_ali, *n_coh, *n_cpl;
   double *steer, *force, *y1, *u1;        /* steering accel, coupling force F_a, new state */
   uint32_t *acnt, *aoff, *asorted;
+  /* the new state before the walls act (after the position update): lets a
+     comparison tell a reflection decided on a value within rounding of a wall */
+  double *x1f, *v1f, *y1f, *u1f;
 } orc_out;
 
 /* Grid derived from the parameters: cell size d = fl32(R (1 + 2^-10)) with
@@ -67,8 +70,19 @@ int orc_step_ex(const orc_params* p, int64_t n, const float* x, const float* v, 
                 const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
                 const double* agent_acc, orc_out* out);
 
-/* Number of OpenMP threads the oracle runs with. */
+/* orc_step_ex with the densities of the force terms given (rho_in[n], id
+   order, may be NULL): the pressure, viscosity and coupling terms use
+   rho_in[i] in place of the computed density of particle i, while out->rho
+   still receives the computed one.  Lets a comparison separate the force
+   arithmetic from the density it is fed. */
+int orc_step_rho(const orc_params* p, int64_t n, const float* x, const float* v, int64_t na, const float* y,
+                 const float* u, const int64_t* fsample, int64_t n_fs, const int64_t* asample, int64_t n_as,
+                 const double* agent_acc, const double* rho_in, orc_out* out);
+
+/* Number of OpenMP threads the oracle runs with, and a way to change it
+   (n <= 0 leaves it). */
 int orc_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -103,7 +103,7 @@ class Info(ctypes.Structure):
 
 
 EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_bytes", "sph_info_get",
-           "sph_capture", "sph_step_profiled", "sph_step_timed", "sph_phase_name", "sph_autotune", "sph_tuning_set",
+           "sph_capture", "sph_abort_set", "sph_step_profiled", "sph_step_timed", "sph_phase_name", "sph_autotune", "sph_tuning_set",
            "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_destroy", "sph_last_error",
            "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
            "sph_closure_adam_step", "sph_closure_weights", "sph_closure_destroy", "sph_closure_last_error",
@@ -138,6 +138,8 @@ def lib() -> ctypes.CDLL:
         L.sph_field_bytes.argtypes = [vp, i32]
         L.sph_info_get.restype = ctypes.c_int
         L.sph_info_get.argtypes = [vp, ctypes.POINTER(Info)]
+        L.sph_abort_set.restype = ctypes.c_int
+        L.sph_abort_set.argtypes = [vp, i32]
         L.sph_capture.restype = ctypes.c_int
         L.sph_capture.argtypes = [vp, i32]
         L.sph_step_profiled.restype = ctypes.c_int
@@ -277,6 +279,10 @@ class Simulation:
     # -- calls ------------------------------------------------------------
     def step(self, n: int = 1) -> None:
         _check(lib().sph_step(self._ctx, int(n)), self._ctx)
+
+    def set_abort(self, raise_flag: bool) -> None:
+        """Raise or clear the fused step's sticky abort flag (sph_abort_set)."""
+        _check(lib().sph_abort_set(self._ctx, int(bool(raise_flag))), self._ctx)
 
     def capture(self, n: int) -> None:
         _check(lib().sph_capture(self._ctx, int(n)), self._ctx)

@@ -329,6 +329,8 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
 
   hipStream_t st = ctx->stream;
   CHK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+  CHK(hipHostMalloc((void**)&ctx->h_abort, 4, hipHostMallocDefault));
+  *ctx->h_abort = 0;
   // tables
   std::vector<SortSet> sets(nsets);
   for (int t = 0; t < nsets; ++t) {
@@ -538,6 +540,12 @@ sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st) {
     F.bar = ctx->d_bar;
     F.abort_flag = ctx->d_abort;
     for (int32_t k = 0; k < n_steps; ++k) launch_step_fused(F, ctx->fused_variant, st);
+    // the host copy of the abort flag lands when these steps are done
+    if (n_steps > 0) {
+      hipError_t e = hipMemcpyAsync(ctx->h_abort, ctx->d_abort, 4, hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return fail(ctx, SPH_EHIP, "abort flag copy: %s", hipGetErrorString(e));
+      ctx->fused_ran = true;
+    }
   } else {
     for (int32_t k = 0; k < n_steps; ++k)
       for (int p = 0; p < kStepPhases; ++p) launch_phase(ctx, p, st);
@@ -703,6 +711,30 @@ static sph_status check_finite(sph_ctx* ctx) {
   HIPCHK(hipStreamSynchronize(st));
   if (aborted) return fail(ctx, SPH_EHIP, "a grid barrier of the fused step timed out");
   if (flag) return fail(ctx, SPH_ENONFINITE, "non-finite position or velocity in the state");
+  return SPH_OK;
+}
+
+// A fused step whose grid barrier timed out leaves a half-updated state and
+// makes every later fused launch a no-op.  The host copy of the flag tells
+// sph_step without waiting; sph_read waits for the stream and asks the device.
+static bool abort_seen(const sph_ctx* ctx) {
+  return ctx->h_abort && __atomic_load_n(ctx->h_abort, __ATOMIC_ACQUIRE) != 0;
+}
+
+static sph_status abort_status(sph_ctx* ctx) {
+  return fail(ctx, SPH_EHIP, "a grid barrier of the fused step timed out; the state is invalid until "
+                             "sph_abort_set(ctx, 0) and a restored state");
+}
+
+static sph_status check_abort_sync(sph_ctx* ctx) {
+  if (!ctx->fused_ran) return SPH_OK;
+  int aborted = 0;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(&aborted, ctx->d_abort, 4, hipMemcpyDeviceToHost));
+  if (aborted) {
+    __atomic_store_n(ctx->h_abort, 1, __ATOMIC_RELEASE);
+    return abort_status(ctx);
+  }
   return SPH_OK;
 }
 
@@ -1136,6 +1168,7 @@ sph_status sph_create_batch(const sph_params* per_scene, int32_t n_scenes, const
 sph_status sph_step(sph_ctx* ctx, int32_t n_steps) {
   if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
   if (n_steps < 0) return fail(ctx, SPH_EINVAL, "n_steps must be >= 0");
+  if (abort_seen(ctx)) return abort_status(ctx);
   if (n_steps == 0) return SPH_OK;
   sph_status s;
   if (ctx->graph_exec && ctx->graph_steps == n_steps) {
@@ -1147,6 +1180,7 @@ sph_status sph_step(sph_ctx* ctx, int32_t n_steps) {
   }
   if (s != SPH_OK) return s;
   ctx->steps += n_steps;
+  if (abort_seen(ctx)) return abort_status(ctx);
   s = check_list_status(ctx);
   if (s != SPH_OK) return s;
   if (ctx->check_finite) return check_finite(ctx);
@@ -1207,7 +1241,23 @@ const char* sph_phase_name(int32_t phase) {
 
 sph_status sph_read(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_bytes) {
   if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  sph_status s = check_abort_sync(ctx);
+  if (s != SPH_OK) return s;
   return sph_read_impl(ctx, field, dst, dst_bytes);
+}
+
+sph_status sph_abort_set(sph_ctx* ctx, int32_t raise) {
+  if (!ctx) return fail(nullptr, SPH_EINVAL, "NULL context");
+  const int v = raise ? 1 : 0;
+  const uint32_t bar0 = 0;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(ctx->d_abort, &v, 4, hipMemcpyHostToDevice));
+  if (!raise) {
+    // an aborted barrier can leave a partial arrival count behind
+    HIPCHK(hipMemcpy(ctx->d_bar, &bar0, 4, hipMemcpyHostToDevice));
+    __atomic_store_n(ctx->h_abort, 0, __ATOMIC_RELEASE);
+  }
+  return SPH_OK;
 }
 
 int64_t sph_field_bytes(const sph_ctx* ctx, int32_t field) {
@@ -1242,6 +1292,7 @@ void sph_destroy(sph_ctx* ctx) {
   for (auto e : ctx->prof_ev) (void)hipEventDestroy(e);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->staging) (void)hipFree(ctx->staging);
+  if (ctx->h_abort) (void)hipHostFree(ctx->h_abort);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->cl_arena) (void)hipFree(ctx->cl_arena);
   if (ctx->list_arena) (void)hipFree(ctx->list_arena);

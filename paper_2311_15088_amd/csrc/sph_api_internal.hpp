@@ -63,6 +63,8 @@ struct sph_ctx {
   int fused_variant = 0;
   uint32_t* d_bar;   // [2] grid-barrier counter, generation
   int* d_abort;      // fused barrier timed out (sticky)
+  int* h_abort = nullptr;  // pinned host copy of d_abort, refreshed after every fused launch
+  bool fused_ran = false;  // fused steps were enqueued (sph_read then checks d_abort)
   float tuned_ms = 0.0f;
 
   hipGraph_t graph = nullptr;

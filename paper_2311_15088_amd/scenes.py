@@ -256,6 +256,50 @@ def small_dam(nx=12, ny=10, nz=14, h=0.05, n_agents=24, agents="inside", seed=SE
     return dam_break("small", nx, ny, nz, h, (0, 0, 0), box_max, n_agents, dt, 5, seed, agents=agents)
 
 
+def wall_scene():
+    """Particles and agents placed just inside each wall, edge and corner of
+    the unit box, moving outward fast enough that one step (dt = 5e-4, h =
+    0.05) carries them through the wall, or, for a second set, not quite to
+    it.  Returns (params, x, v, y, u, dt)."""
+    p = default_params(0.05, 5e-4, (0, 0, 0), (1, 1, 1))
+    dt = p["dt"]
+    pts, vel = [], []
+    # one particle per wall, crossing by 3e-4 (speed 1 over dt = 5e-4 from 2e-4 inside)
+    # and a partner 3h away that stops 3e-4 short of the wall
+    for axis in range(3):
+        for side in (0, 1):
+            for inset, tag in ((2e-4, "cross"), (8e-4, "short")):
+                x = np.full(3, 0.5)
+                x[(axis + 1) % 3] = 0.3 if tag == "cross" else 0.7
+                x[axis] = inset if side == 0 else 1.0 - inset
+                v = np.zeros(3)
+                v[axis] = (-1.0 if side == 0 else 1.0)
+                pts.append(x)
+                vel.append(v)
+    # corners and edges: crossing two and three walls at once
+    for c in ((0, 0, 0), (1, 1, 1), (0, 1, 0), (1, 0, 1), (0, 0, 1)):
+        c = np.asarray(c, np.float64)
+        x = np.where(c == 0, 2e-4, 1.0 - 2e-4)
+        v = np.where(c == 0, -1.0, 1.0)
+        pts.append(x)
+        vel.append(v)
+    for e in ((0, 0, 0.5), (1, 0.5, 1)):
+        e = np.asarray(e, np.float64)
+        x = np.where(e == 0, 3e-4, np.where(e == 1, 1.0 - 3e-4, 0.5))
+        v = np.where(e == 0, -1.0, np.where(e == 1, 1.0, 0.0))
+        pts.append(x)
+        vel.append(v)
+    # a particle on the wall, moving out, and one on the wall moving in
+    pts += [np.array([0.0, 0.2, 0.2]), np.array([1.0, 0.8, 0.8])]
+    vel += [np.array([-0.5, 0.0, 0.0]), np.array([-0.5, 0.0, 0.0])]
+    x = np.asarray(pts, np.float32)
+    v = np.asarray(vel, np.float32)
+    # agents: at top speed (v_max) through the walls
+    ya = np.array([[3e-4, 0.5, 0.5], [0.5, 1 - 3e-4, 0.5], [0.5, 0.5, 3e-4], [1 - 1e-4, 1e-4, 1 - 1e-4]], np.float32)
+    ua = np.array([[-1, 0, 0], [0, 1, 0], [0, 0, -1], [0.577, -0.577, 0.577]], np.float32)
+    return p, x, v, ya, ua, dt
+
+
 def clumped_dam(n_clump: int = 1500, side_cells: float = 2.0, seed: int = SEED0 + 0x778) -> Scene:
     """small_dam plus a dense clump: n_clump extra particles uniform in a cube of
     side_cells grid cells inside the fluid (a compressed region: cells far above

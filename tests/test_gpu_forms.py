@@ -113,3 +113,47 @@ def test_invalid_tuning_is_rejected():
             sim.set_tuning(*bad)
         assert ei.value.status == sph.EINVAL
     sim.close()
+
+
+def test_fused_abort_is_reported_and_leaves_the_state():
+    """The fused step's sticky abort flag (what a timed-out grid barrier
+    raises), set from the host: the fused kernel leaves at entry, so nothing
+    hangs and the state is untouched; sph_read and every later sph_step report
+    SPH_EHIP; clearing the flag re-arms the fused step."""
+    sc = scenes.config0c()
+    sim = sph.create(sc)
+    sim.set_tuning(1, 0, 32)
+    sim.step(2)
+    before = state(sim)
+    sim.set_abort(True)
+    try:
+        sim.step(1)  # enqueued; the flag's host copy may not have landed yet
+    except sph.SphError as e:
+        assert e.status == sph.EHIP
+    with pytest.raises(sph.SphError) as ei:
+        sim.read(sph.POS)
+    assert ei.value.status == sph.EHIP
+    with pytest.raises(sph.SphError) as ei:
+        sim.step(1)
+    assert ei.value.status == sph.EHIP
+    sim.set_abort(False)
+    same(before, state(sim))  # the aborted launch wrote nothing
+    sim.step(1)
+    ref = sph.create(sc)
+    ref.step(3)
+    same(state(ref), state(sim))
+    ref.close()
+    sim.close()
+
+
+def test_abort_flag_does_not_touch_per_phase_steps():
+    sc = scenes.config0c()
+    sim = sph.create(sc)
+    sim.step(1)  # per-phase launches never read the flag
+    sim.set_abort(False)
+    sim.step(1)
+    ref = sph.create(sc)
+    ref.step(2)
+    same(state(ref), state(sim))
+    ref.close()
+    sim.close()

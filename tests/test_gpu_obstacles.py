@@ -9,7 +9,7 @@ import oracle
 import paper_2311_15088_amd as sph
 from oracle import obstacles
 from paper_2311_15088_amd import scenes
-from parity import compare_step
+from parity import compare_step, oracle_given_rho
 from test_gpu_parity import gpu_fields, state
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +38,8 @@ def test_obstacle_parity_against_oracle():
         sim.step(1)
         g = gpu_fields(sim)
         ref = oracle.step(sc.params, x, v, y, u, agent_acc=acc)
-        compare_step(g, ref, sc.params)
+        refc = oracle_given_rho(oracle, sc.params, x, v, y, u, g["rho"], agent_acc=acc)
+        compare_step(g, ref, sc.params, x, y, ref_rho=refc)
         x, v, y, u = g["x1"], g["v1"], g["y1"], g["u1"]
     assert touched >= 10
     sim.close()

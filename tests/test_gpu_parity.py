@@ -11,7 +11,7 @@ import oracle
 import paper_2311_15088_amd as sph
 from paper_2311_15088_amd import scenes
 
-from parity import compare_step
+from parity import compare_step, oracle_given_rho
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +42,9 @@ def chained_parity(sc, steps, fs=None, as_=None, nbr_mode=0, search=sph.SEARCH_T
         sim.step(1)
         g = gpu_fields(sim)
         ref = oracle.step(sc.params, x, v, y, u, fsample=fs, asample=as_, nbr_mode=nbr_mode)
+        refc = oracle_given_rho(oracle, sc.params, x, v, y, u, g["rho"], fsample=fs, asample=as_, nbr_mode=nbr_mode)
         rep = {}
-        compare_step(g, ref, sc.params, fs=fs, as_=as_, report=rep)
+        compare_step(g, ref, sc.params, x, y, fs=fs, as_=as_, report=rep, ref_rho=refc)
         for kk, vv in rep.items():
             worst[kk] = max(worst.get(kk, 0.0), vv)
         x, v, y, u = g["x1"], g["v1"], g["y1"], g["u1"]
@@ -113,8 +114,9 @@ def test_config1_full_size_sampled_graph():
                                    np.arange(sc.n - 64, sc.n)]))
     as_ = np.arange(sc.n_agents)
     ref = oracle.step(sc.params, x, v, y, u, fsample=fs, asample=as_, nbr_mode=1)
+    refc = oracle_given_rho(oracle, sc.params, x, v, y, u, g["rho"], fsample=fs, asample=as_, nbr_mode=1)
     rep = {}
-    compare_step(g, ref, sc.params, fs=fs, as_=as_, report=rep)
+    compare_step(g, ref, sc.params, x, y, fs=fs, as_=as_, report=rep, ref_rho=refc)
     print("[parity] config1 errors:", {k: f"{v:.2e}" for k, v in rep.items()}, flush=True)
     pairs = sim.read(sph.PAIR_COUNT)[0]
     assert pairs > 25 * sc.n * 2  # two steps with ~30 neighbours each
@@ -136,8 +138,9 @@ def test_config2_full_size_sampled():
                                    np.arange(sc.n - 32, sc.n)]))
     as_ = np.unique(rng.choice(sc.n_agents, 256, replace=False))
     ref = oracle.step(sc.params, x, v, y, u, fsample=fs, asample=as_, nbr_mode=1)
+    refc = oracle_given_rho(oracle, sc.params, x, v, y, u, g["rho"], fsample=fs, asample=as_, nbr_mode=1)
     rep = {}
-    compare_step(g, ref, sc.params, fs=fs, as_=as_, report=rep)
+    compare_step(g, ref, sc.params, x, y, fs=fs, as_=as_, report=rep, ref_rho=refc)
     print("[parity] config2 errors:", {k: f"{v:.2e}" for k, v in rep.items()}, flush=True)
     sim.close()
 
@@ -230,6 +233,7 @@ def test_batched_parity_against_oracle():
         p0, p1 = bat.part_off[s], bat.part_off[s + 1]
         a0, a1 = bat.agent_off[s], bat.agent_off[s + 1]
         ref = oracle.step(sc.params, sc.x, sc.v, sc.y, sc.u)
+        refc = oracle_given_rho(oracle, sc.params, sc.x, sc.v, sc.y, sc.u, g_all["rho"][p0:p1])
         nc = len(ref["off"])
         c0 = sum(oracle.grid(scs[t].params)[3] + 1 for t in range(s))
         ac0 = sum(oracle.grid(scs[t].params, True)[3] + 1 for t in range(s))
@@ -243,7 +247,7 @@ def test_batched_parity_against_oracle():
                 g[k] = val[a0:a1]
             else:
                 g[k] = val[p0:p1]
-        compare_step(g, ref, sc.params)
+        compare_step(g, ref, sc.params, sc.x, sc.y, ref_rho=refc)
     bat.close()
 
 
@@ -297,4 +301,32 @@ def test_diagnostics_need_the_flag():
     with pytest.raises(sph.SphError) as ei:
         sim.read(sph.ACC_INT)
     assert ei.value.status == sph.ESTATE
+    sim.close()
+
+
+def test_walls_per_element():
+    """Every particle and agent is compared, position and velocity, against
+    the oracle in a step that carries them through the walls: both sides must
+    take the same reflection decisions, and the displacement of each element
+    must agree to 1e-4 of the displacement scale (plus float32 rounding)."""
+    p, x, v, y, u, dt = scenes.wall_scene()
+    sim = sph.Simulation(p, x, v, y, u, flags=sph.FLAG_DIAGNOSTICS)
+    for k in range(2):
+        print(f"[parity] walls step {k}", flush=True)
+        sim.step(1)
+        g = gpu_fields(sim)
+        ref = oracle.step(p, x, v, y, u)
+        refc = oracle_given_rho(oracle, p, x, v, y, u, g["rho"])
+        rep = {}
+        compare_step(g, ref, p, x, y, report=rep, ref_rho=refc)
+        print("[parity] walls:", rep, flush=True)
+        assert rep["x_wall_ambiguous"] == 0 and rep["y_wall_ambiguous"] == 0
+        if k == 0:
+            # 6 single walls, 5 corners (2 or 3 walls), 2 edges and the particle on a wall
+            assert rep["x_wall_reflections"] == 6 + (3 + 3 + 3 + 3 + 3) + 4 + 1
+            assert rep["y_wall_reflections"] == 1 + 1 + 1 + 3
+            # every reflected coordinate is inside the box, mirrored by its overshoot
+            gx = g["x1"].astype(np.float64)
+            assert (gx >= 0).all() and (gx <= 1).all()
+        x, v, y, u = g["x1"], g["v1"], g["y1"], g["u1"]
     sim.close()
