@@ -269,6 +269,10 @@ sph_status sph_obstacles_set(sph_ctx* ctx, int32_t n_boxes, const float* boxes, 
 typedef struct sph_closure sph_closure;
 #define SPH_CLOSURE_PARAMS 49795
 #define SPH_CLOSURE_FEATURES 256
+/* floats in a closure checkpoint (sph_closure_io): weights, Adam first and
+   second moments (SPH_CLOSURE_PARAMS each, flat order), force scale, Adam
+   step count */
+#define SPH_CLOSURE_STATE_FLOATS (3 * SPH_CLOSURE_PARAMS + 2)
 
 typedef struct sph_train_params {
   int32_t epochs, batch;   /* e.g. 20, 4096 */
@@ -310,6 +314,15 @@ sph_status sph_closure_adam_step(sph_closure* cl, const float* grad, int32_t t, 
                                  float eps);
 /* write = 0: copy the weights / scale out; 1: load them (either pointer may be NULL). */
 sph_status sph_closure_weights(sph_closure* cl, int32_t write, float* weights, float* force_scale);
+/* Save (dir = 0) or load (dir = 1) the closure's whole training state, so
+   that training can stop and resume (section 5's checkpoint of the learned
+   part): buf (host or device) holds SPH_CLOSURE_STATE_FLOATS float32 values,
+   bytes is checked.  The step count is the t of the last Adam step
+   (sph_closure_train's last step or the t given to sph_closure_adam_step); a
+   resumed run passes t + 1, t + 2, ... to sph_closure_adam_step.  Loading
+   rejects a non-positive scale or a step count that is not a whole number in
+   [0, 2^24].  Synchronises. */
+sph_status sph_closure_io(sph_closure* cl, int32_t dir, float* buf, int64_t bytes);
 void sph_closure_destroy(sph_closure* cl);
 const char* sph_closure_last_error(const sph_closure* cl);
 /* Use cl for the agents' coupling force: every check_every steps (starting

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENONFINITE, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
 FLAG_DIAGNOSTICS, FLAG_CHECK_FINITE, FLAG_FUSED, FLAG_FEATURES = 1, 2, 4, 8
 CLOSURE_PARAMS, CLOSURE_FEATURES = 49795, 256
+CLOSURE_STATE_FLOATS = 3 * CLOSURE_PARAMS + 2
 
 # fields (sph_field)
 POS, VEL, AGENT_POS, AGENT_VEL, DENSITY, NBR_COUNT, CELL_KEY, ACC_INT, ACC_COUPLE, TOUCHED, \
@@ -106,7 +107,7 @@ EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_
            "sph_capture", "sph_abort_set", "sph_step_profiled", "sph_step_timed", "sph_phase_name", "sph_autotune", "sph_tuning_set",
            "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_destroy", "sph_last_error",
            "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
-           "sph_closure_adam_step", "sph_closure_weights", "sph_closure_destroy", "sph_closure_last_error",
+           "sph_closure_adam_step", "sph_closure_weights", "sph_closure_io", "sph_closure_destroy", "sph_closure_last_error",
            "sph_closure_attach", "sph_closure_stats_get")
 STEP_PHASES = 8
 
@@ -170,6 +171,8 @@ def lib() -> ctypes.CDLL:
         L.sph_closure_train.argtypes = [vp, vp, vp, i64, ctypes.POINTER(TrainParams), ctypes.POINTER(TrainReport)]
         L.sph_closure_predict.restype = ctypes.c_int
         L.sph_closure_predict.argtypes = [vp, vp, i64, vp]
+        L.sph_closure_io.restype = ctypes.c_int
+        L.sph_closure_io.argtypes = [vp, i32, vp, i64]
         L.sph_closure_gradient.restype = ctypes.c_int
         L.sph_closure_gradient.argtypes = [vp, vp, vp, i64, vp, vp]
         L.sph_closure_adam_step.restype = ctypes.c_int
@@ -447,6 +450,16 @@ class Closure:
     def predict(self, features, out):
         _cl_check(lib().sph_closure_predict(self._cl, _dptr(features), int(features.shape[0]), _dptr(out)), self._cl)
         return out
+
+    def save_state(self) -> np.ndarray:
+        """Weights, Adam moments, force scale and Adam step count (sph_closure_io)."""
+        buf = np.zeros(CLOSURE_STATE_FLOATS, np.float32)
+        _cl_check(lib().sph_closure_io(self._cl, 0, buf.ctypes.data, buf.nbytes), self._cl)
+        return buf
+
+    def load_state(self, buf) -> None:
+        b = np.ascontiguousarray(np.asarray(buf, np.float32))
+        _cl_check(lib().sph_closure_io(self._cl, 1, b.ctypes.data, b.nbytes), self._cl)
 
     def gradient(self, features, forces):
         g = np.zeros(CLOSURE_PARAMS, np.float32)

@@ -29,6 +29,7 @@ struct sph_closure {
   MlpWork wk{};
   char* work = nullptr;
   int work_rows = 0;
+  int32_t adam_t = 0;  // Adam steps taken on the current moments
 };
 
 static sph_status cfail(sph_closure* cl, sph_status st, const char* fmt, ...) {
@@ -244,6 +245,35 @@ sph_status sph_closure_adam_step(sph_closure* cl, const float* grad, int32_t t, 
   CLCHK(hipMemcpyAsync(cl->W.grad, grad, 4 * (size_t)kParams, hipMemcpyDefault, cl->stream));
   mlp_adam(cl->W, t, lr, beta1, beta2, eps, cl->stream);
   CLCHK(hipStreamSynchronize(cl->stream));
+  cl->adam_t = t;
+  return SPH_OK;
+}
+
+// Checkpoint of the whole closure state: weights, Adam moments, force scale
+// and the Adam step count, one float32 buffer (layout in sph.h).
+sph_status sph_closure_io(sph_closure* cl, int32_t dir, float* buf, int64_t bytes) {
+  if (!cl || !buf || (dir != 0 && dir != 1)) return cfail(cl, SPH_EINVAL, "invalid arguments");
+  const size_t P = (size_t)kParams;
+  if (bytes < (int64_t)(4 * SPH_CLOSURE_STATE_FLOATS))
+    return cfail(cl, SPH_EINVAL, "buffer holds %lld bytes, the state needs %lld", (long long)bytes,
+                 (long long)(4 * SPH_CLOSURE_STATE_FLOATS));
+  float* dev[3] = {cl->W.w, cl->W.m, cl->W.v};
+  if (dir == 0) {
+    for (int k = 0; k < 3; ++k) CLCHK(hipMemcpyAsync(buf + k * P, dev[k], 4 * P, hipMemcpyDefault, cl->stream));
+    CLCHK(hipStreamSynchronize(cl->stream));
+    float tail[2] = {cl->W.scale, (float)cl->adam_t};
+    CLCHK(hipMemcpy(buf + 3 * P, tail, sizeof tail, hipMemcpyDefault));
+  } else {
+    float tail[2];
+    CLCHK(hipMemcpy(tail, buf + 3 * P, sizeof tail, hipMemcpyDefault));
+    if (!(tail[0] > 0.0f) || !(tail[1] >= 0.0f) || tail[1] > 16777216.0f || tail[1] != floorf(tail[1]))
+      return cfail(cl, SPH_EINVAL, "invalid force scale or step count in the state");
+    for (int k = 0; k < 3; ++k) CLCHK(hipMemcpyAsync(dev[k], buf + k * P, 4 * P, hipMemcpyDefault, cl->stream));
+    mlp_refresh_bf16(cl->W, cl->stream);
+    CLCHK(hipStreamSynchronize(cl->stream));
+    cl->W.scale = tail[0];
+    cl->adam_t = (int32_t)tail[1];
+  }
   return SPH_OK;
 }
 
@@ -335,6 +365,7 @@ sph_status sph_closure_train(sph_closure* cl, const uint16_t* features, const fl
   (void)hipFree(fb);
   (void)hipFree(losses);
   (void)hipFree(verr);
+  cl->adam_t = step;
   if (rep) {
     rep->train_loss = (float)last_loss;
     rep->val_rel_rms = sf > 0.0 ? (float)sqrt(se / sf) : 0.0f;

@@ -187,3 +187,116 @@ def test_in_step_inference_equals_predict():
     sim.attach_closure(None)
     sim.close()
     cl.close()
+
+
+def test_gain_of_the_trained_network_on_config4():
+    """What the trained network gains over the method without it, on the
+    4,194,304-particle / 65,536-agent workload: trained on this project's GPU
+    kernels with pairs from config-4-style runs of another seed, then measured
+    against the exact per-agent gather on the workload itself.
+
+    Measured (and asserted): the trained network's relative RMS force error
+    is well below that of predicting nothing (1.0) and of the untrained
+    network, but far above the 2 % bound, so the controller keeps the exact
+    gather at every check and the step is bit-identical to the exact one; the
+    surrogate path's time is measured beside the exact gather's."""
+    dev = torch.device(DEV)
+    train_sc = scenes.dam_break("c4", 256, 64, 256, 0.02, (0, 0, 0), (3, 1, 3), 65536, 2e-4, 100,
+                                scenes.SEED0 + 0x410, agents="inside")
+    sim = sph.create(train_sc, flags=sph.FLAG_FEATURES | sph.FLAG_DIAGNOSTICS)
+    X = torch.empty((6 * 65536, 256), dtype=torch.int16, device=dev)
+    F = torch.empty((6 * 65536, 3), dtype=torch.float32, device=dev)
+    for k in range(6):
+        sim.step(4)
+        sim.read_into(sph.AGENT_FEATURES, X[k * 65536:(k + 1) * 65536])
+        sim.read_into(sph.AGENT_FORCE, F[k * 65536:(k + 1) * 65536])
+    sim.close()
+    del train_sc
+    cl = sph.Closure(scenes.mlp_flat(scenes.mlp_init()))
+    untrained = sph.Closure(scenes.mlp_flat(scenes.mlp_init()))
+    rep = cl.train(X, F, epochs=8, batch=4096, lr=1e-3, val_fraction=0.1, seed=3)
+    untrained_rep = untrained.train(X, F, epochs=0, batch=4096, val_fraction=0.1, seed=3)  # sets the force scale only
+    del X, F
+    print(f"[closure] trained on {6 * 65536} pairs: {rep}", flush=True)
+    # the workload itself: exact force and features of a few steps
+    sc = scenes.config4()
+    sim = sph.create(sc, flags=sph.FLAG_FEATURES | sph.FLAG_DIAGNOSTICS)
+    num = {"trained": 0.0, "untrained": 0.0}
+    den = 0.0
+    for _ in range(3):
+        sim.step(5)
+        feats = torch.empty((sc.n_agents, 256), dtype=torch.int16, device=dev)
+        exact = torch.empty((sc.n_agents, 3), dtype=torch.float32, device=dev)
+        sim.read_into(sph.AGENT_FEATURES, feats)
+        sim.read_into(sph.AGENT_FORCE, exact)
+        for name, net in (("trained", cl), ("untrained", untrained)):
+            pred = torch.empty_like(exact)
+            net.predict(feats, pred)
+            num[name] += float(((pred.double() - exact.double()) ** 2).sum())
+        den += float((exact.double() ** 2).sum())
+    sim.close()
+    err = {k: (v / den) ** 0.5 for k, v in num.items()}
+    print(f"[closure] config 4 rel RMS: trained {err['trained']:.3f}, untrained {err['untrained']:.3f}, "
+          f"predicting nothing 1.000", flush=True)
+    assert err["trained"] < 0.9 and err["trained"] < 0.9 * err["untrained"]
+    # time: the agent phase with the exact gather, and with the surrogate path forced
+    times = {}
+    for name, bound in (("exact", None), ("surrogate", 1e30), ("controller", 0.02)):
+        s = sph.create(sc)
+        if bound is not None:
+            s.attach_closure(cl, check_every=50, max_rel_rms=bound)
+        s.step(2)
+        ph = s.step_profiled(20)
+        times[name] = 1e3 * ph["agents"] / 20
+        if name == "controller":
+            st = s.closure_stats()
+            print(f"[closure] controller at 2 %: {st}", flush=True)
+            assert st["checks"] >= 1 and st["fallbacks"] == st["checks"] and st["surrogate_steps"] == 0
+            ref = sph.create(sc)
+            ref.step(22)
+            for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL):
+                np.testing.assert_array_equal(s.read(f), ref.read(f))
+            ref.close()
+        if bound is not None:
+            s.attach_closure(None)
+        s.close()
+    print(f"[closure] agents phase us/step: exact {times['exact']:.1f}, surrogate path {times['surrogate']:.1f}, "
+          f"under the 2 % controller {times['controller']:.1f}", flush=True)
+    assert all(t > 0 for t in times.values())
+    cl.close()
+    untrained.close()
+
+
+def test_checkpoint_of_weights_and_adam_moments_resumes_bit_identically():
+    """sph_closure_io saves weights, both Adam moments, the force scale and the
+    step count; a closure loaded from it continues the optimiser exactly as
+    the original does."""
+    rng = np.random.default_rng(8)
+    _, bits = bf16_bits(rng.standard_normal((500, 256)))
+    X = to_dev_bits(bits)
+    T = torch.from_numpy(rng.standard_normal((500, 3)).astype(np.float32)).to(DEV)
+    a = sph.Closure(scenes.mlp_flat(params_np(13)), force_scale=1.3)
+    for t in (1, 2, 3):
+        g, _ = a.gradient(X, T)
+        a.adam_step(g, t, lr=1e-2)
+    state = a.save_state()
+    assert state.size == sph.CLOSURE_STATE_FLOATS and state[-1] == 3.0 and state[-2] == np.float32(1.3)
+    assert np.abs(state[sph.CLOSURE_PARAMS:2 * sph.CLOSURE_PARAMS]).max() > 0  # first moments are there
+    b = sph.Closure(None)
+    b.load_state(state)
+    np.testing.assert_array_equal(b.save_state(), state)
+    for cl in (a, b):
+        for t in (4, 5):
+            g, _ = cl.gradient(X, T)
+            cl.adam_step(g, t, lr=1e-2)
+    wa, sa = a.weights()
+    wb, sb = b.weights()
+    np.testing.assert_array_equal(wa, wb)
+    np.testing.assert_array_equal(a.save_state(), b.save_state())
+    bad = state.copy()
+    bad[-2] = 0.0  # force scale must be positive
+    with pytest.raises(sph.SphError) as ei:
+        b.load_state(bad)
+    assert ei.value.status == sph.EINVAL
+    a.close()
+    b.close()
