@@ -304,6 +304,17 @@ sph_status sph_closure_train(sph_closure* cl, const uint16_t* features, const fl
                              const sph_train_params* params, sph_train_report* report);
 /* forces [n][3] = MLP(features) * force_scale (device pointers; asynchronous). */
 sph_status sph_closure_predict(sph_closure* cl, const uint16_t* features, int64_t n, float* forces);
+/* sph_closure_predict without any allocation, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): the forward pass's activations live in a
+   fixed device array of the library (33.6 MB on every device the library
+   runs on, held until the process ends) instead of the closure's work
+   buffers, which sph_closure_predict grows with hipMalloc.  n <= 65,536 rows
+   per call (SPH_ECAPACITY beyond; split larger inputs).  Same arguments and
+   the same results as sph_closure_predict.  Every call on one device shares
+   that array, so calls that overlap on one device (different streams, or
+   several host threads) race; serialise them. */
+sph_status sph_closure_predict_static(sph_closure* cl, const uint16_t* features, int64_t n, float* forces);
 /* Gradient of the mean squared error between MLP(features) and forces /
    force_scale with respect to the weights (flat order), and that loss;
    device pointers for the inputs, host or device for grad / loss; synchronises. */

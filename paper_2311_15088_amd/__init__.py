@@ -106,7 +106,7 @@ class Info(ctypes.Structure):
 EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_bytes", "sph_info_get",
            "sph_capture", "sph_abort_set", "sph_step_profiled", "sph_step_timed", "sph_phase_name", "sph_autotune", "sph_tuning_set",
            "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_destroy", "sph_last_error",
-           "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_gradient",
+           "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_predict_static", "sph_closure_gradient",
            "sph_closure_adam_step", "sph_closure_weights", "sph_closure_io", "sph_closure_destroy", "sph_closure_last_error",
            "sph_closure_attach", "sph_closure_stats_get")
 STEP_PHASES = 8
@@ -171,6 +171,8 @@ def lib() -> ctypes.CDLL:
         L.sph_closure_train.argtypes = [vp, vp, vp, i64, ctypes.POINTER(TrainParams), ctypes.POINTER(TrainReport)]
         L.sph_closure_predict.restype = ctypes.c_int
         L.sph_closure_predict.argtypes = [vp, vp, i64, vp]
+        L.sph_closure_predict_static.restype = ctypes.c_int
+        L.sph_closure_predict_static.argtypes = [vp, vp, i64, vp]
         L.sph_closure_io.restype = ctypes.c_int
         L.sph_closure_io.argtypes = [vp, i32, vp, i64]
         L.sph_closure_gradient.restype = ctypes.c_int
@@ -449,6 +451,13 @@ class Closure:
 
     def predict(self, features, out):
         _cl_check(lib().sph_closure_predict(self._cl, _dptr(features), int(features.shape[0]), _dptr(out)), self._cl)
+        return out
+
+    def predict_static(self, features, out):
+        """predict() without allocating: activations in the library's fixed device array
+        (at most 65,536 rows per call)."""
+        _cl_check(lib().sph_closure_predict_static(self._cl, _dptr(features), int(features.shape[0]), _dptr(out)),
+                  self._cl)
         return out
 
     def save_state(self) -> np.ndarray:

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -219,6 +220,59 @@ sph_status sph_closure_predict(sph_closure* cl, const uint16_t* features, int64_
   if (s != SPH_OK) return s;
   mlp_forward(cl->W, features, (int)n, cl->wk, cl->stream);
   hipLaunchKernelGGL(k_scale_out, dim3((3 * n + 255) / 256), dim3(256), 0, cl->stream, cl->wk.y, cl->W.scale, (int)n,
+                     forces);
+  CLCHK(hipGetLastError());
+  return SPH_OK;
+}
+
+// ------------------------------------------------- allocation-free predict --
+// sph_closure_predict_static runs the same forward pass as sph_closure_predict
+// with its activations in a fixed device array instead of the closure's work
+// buffers (which grow with hipMalloc): the two hidden layers' bfloat16
+// activations and the unscaled outputs of up to kStaticRows rows.
+constexpr int kStaticRows = 65536;  // one config-4 agent set per call
+constexpr size_t kStaticH = (size_t)kStaticRows * kHid * 2;  // one bf16 hidden layer
+constexpr size_t kStaticBytes = 2 * kStaticH + (size_t)kStaticRows * kOut * 4;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+static char* g_scratch_ptr[kMaxDevices];
+static std::once_flag g_scratch_once[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device with that device current (the array's name is a host-side stand-in
+// and must never be passed to a kernel).
+static char* scratch_ptr(int dev, hipError_t* err) {
+  std::call_once(g_scratch_once[dev], [dev]() {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? (char*)p : nullptr;
+  });
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+
+sph_status sph_closure_predict_static(sph_closure* cl, const uint16_t* features, int64_t n, float* forces) {
+  if (!cl || (n > 0 && (!features || !forces)) || n < 0) return cfail(cl, SPH_EINVAL, "invalid arguments");
+  if (n > kStaticRows)
+    return cfail(cl, SPH_ECAPACITY, "%lld rows exceed the static scratch of %d rows; split the call",
+                 (long long)n, kStaticRows);
+  if (n == 0) return SPH_OK;
+  int dev = 0;
+  CLCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return cfail(cl, SPH_EINVAL, "device %d out of range", dev);
+  hipError_t e = hipSuccess;
+  char* base = scratch_ptr(dev, &e);
+  if (!base) return cfail(cl, SPH_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  MlpWork wk{};
+  wk.rows = (int)n;
+  wk.h1 = (uint16_t*)base;
+  wk.h2 = (uint16_t*)(base + kStaticH);
+  wk.y = (float*)(base + 2 * kStaticH);
+  // z1, z2 (kept for a backward pass) are not written: the GEMM epilogue skips a null Z
+  mlp_forward(cl->W, features, (int)n, wk, cl->stream);
+  hipLaunchKernelGGL(k_scale_out, dim3((3 * n + 255) / 256), dim3(256), 0, cl->stream, wk.y, cl->W.scale, (int)n,
                      forces);
   CLCHK(hipGetLastError());
   return SPH_OK;
