@@ -63,10 +63,16 @@ static const FluidVariant* variants() {
       make_variant<256, 256, 256, 256>(256, "bd256_win256_256"),
       make_variant<512, 1024, 256, 512>(256, "d512_win1024_f256_win512"),
       make_variant<1024, 1024, 256, 512>(256, "d1024_win1024_f256_win512"),
+      // more than one own particle per thread: work items of up to two or
+      // four blocks' worth of particles (each thread takes particles i,
+      // i + BD, ...), so a dense tile re-stages its halo rows less often
+      make_variant<512, 512, 256, 512>(512, "d512_f256_ppt2"),
+      make_variant<256, 512, 256, 512>(512, "bd256_ppt2"),
+      make_variant<256, 512, 256, 512>(1024, "bd256_ppt4"),
   };
   return v;
 }
-constexpr int kNumVariants = 8;
+constexpr int kNumVariants = 11;
 constexpr int kAgentBD = 256;
 
 int fluid_variants() { return kNumVariants; }
