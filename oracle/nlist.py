@@ -8,8 +8,9 @@ keys and the (key, id) order come from the C oracle's step.
 particle's list holds the particles of the 27 cells around its own cell
 whose squared distance to it is below h^2, found by walking those cells in
 the sorted array.  The predicate is the single-precision one of the oracle:
-dx = fl(x_j - x_i) per axis, then fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)),
-against h^2 = fl32(h * h) with h the float32 parameter in double.
+dx = fl(x_j - x_i) per axis, then fl(dz^2 + fl(dy^2 + fl(dx^2))) with the two
+outer steps fused multiply-adds (``oracle/fp32.py``), against h^2 = fl32(h * h)
+with h the float32 parameter in double.
 
 Reading of this project (the paper lists neighbours but does not fix their
 order or whether i itself is kept): each list includes the particle itself
@@ -24,7 +25,7 @@ from typing import Dict, List
 
 import numpy as np
 
-from . import grid, step
+from . import fp32, grid, step
 
 
 def sorted_state(p: Dict, x) -> Dict[str, np.ndarray]:
@@ -54,7 +55,7 @@ def neighbour_lists(p: Dict, x) -> List[np.ndarray]:
         dx = xs[cand, 0] - xs[i, 0]
         dy = xs[cand, 1] - xs[i, 1]
         dz = xs[cand, 2] - xs[i, 2]
-        r2 = (dx * dx + dy * dy) + dz * dz  # float32, each operation rounded
+        r2 = fp32.dist2(dx, dy, dz)  # float32, the outer two steps fused
         keep = cand[r2 < h2]
         # halo row (dz, dy), then sorted index
         row = (d[keep, 2] + 1) * 3 + (d[keep, 1] + 1)

@@ -30,7 +30,7 @@ from typing import Dict, Tuple
 
 import numpy as np
 
-from . import grid
+from . import fp32, grid
 
 
 def mesh_vertices(boxes, spacing: float) -> Tuple[np.ndarray, np.ndarray]:
@@ -112,7 +112,7 @@ def avoidance(p: Dict, y, boxes, spacing: float, weight: float) -> np.ndarray:
                         continue
                     centre = mn + (c.astype(np.float32) + np.float32(0.5)) * cell
                     d = centre - y[a]
-                    d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+                    d2 = fp32.dist2(d[0], d[1], d[2])
                     om = 2.0 if d2 < rsep2 else (1.0 if d2 < rali2 else 0.0)
                     acc += om * mean[key]
         out[a] = w * acc

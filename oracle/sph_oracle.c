@@ -110,16 +110,16 @@ static uint32_t hash_of(const grid_t* g, const int32_t c[3]) {
 }
 
 /* Single-precision squared distance: dx = fl(b - a) per axis, then
-   fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)).  Compiled without contraction. */
+   fl(dz^2 + fl(dy^2 + fl(dx^2))) where the two outer steps are fused
+   multiply-adds (C99 fmaf: the exact product plus sum, rounded once).
+   Compiled without contraction, so nothing else is fused. */
 static float dist2_f32(const float* a, const float* b) {
   float dx = b[0] - a[0];
   float dy = b[1] - a[1];
   float dz = b[2] - a[2];
   float s = dx * dx;
-  float ty = dy * dy;
-  s = s + ty;
-  float tz = dz * dz;
-  s = s + tz;
+  s = fmaf(dy, dy, s);
+  s = fmaf(dz, dz, s);
   return s;
 }
 

@@ -14,9 +14,9 @@ Readings of this project (the paper leaves them open):
     box_min) / spacing) on each axis, x fastest, each coordinate rounded to
     float32 as fl(box_min + fl(c * spacing));
   * i is in the neighbourhood of x when the float32 squared distance (the
-    oracle's predicate: per-axis differences, squares summed in order, each
-    operation rounded) is below fl32(R * R); that integer decision is taken in
-    the same precision on both sides;
+    oracle's predicate: per-axis differences, then fl(dz^2 + fl(dy^2 +
+    fl(dx^2))) with the two outer steps fused) is below fl32(R * R); that
+    integer decision is taken in the same precision on both sides;
   * every particle has the same radius r, so rbar = r whenever the
     neighbourhood is not empty; a corner with an empty neighbourhood has
     phi = +inf (outside any surface).
@@ -26,6 +26,8 @@ from __future__ import annotations
 from typing import Dict, Tuple
 
 import numpy as np
+
+from . import fp32
 
 
 def corner_dims(p: Dict, spacing: float) -> Tuple[int, int, int]:
@@ -46,12 +48,10 @@ def corners(p: Dict, spacing: float) -> np.ndarray:
 
 
 def inside_f32(q: np.ndarray, x: np.ndarray, r2: np.float32) -> np.ndarray:
-    """float32 predicate |x - q|^2 < r2 for one corner q against points x."""
+    """float32 predicate |x - q|^2 < r2 for one corner q against points x
+    (the oracle's squared distance, ``oracle/fp32.py``)."""
     d = x - q[None, :]
-    s = d[:, 0] * d[:, 0]
-    s = s + d[:, 1] * d[:, 1]
-    s = s + d[:, 2] * d[:, 2]
-    return s < r2
+    return fp32.dist2(d[:, 0], d[:, 1], d[:, 2]) < r2
 
 
 def field(p: Dict, x, spacing: float, radius: float, particle_radius: float, sample=None) -> np.ndarray:

@@ -56,16 +56,17 @@ struct SortSet {
 
 // ------------------------------------------------------------------------
 // Exact single-precision predicates.  Contraction is off inside these
-// functions so that every product and sum is rounded on its own, in the
-// order written: this is the definition the reference evaluates too.
+// functions so that every operation is rounded as written: this is the
+// definition the reference evaluates too.  The squared distance is
+// fl(dz^2 + fl(dy^2 + fl(dx^2))) with the two outer steps fused
+// multiply-adds (v_fma_f32: one rounding of the exact product plus sum),
+// three instructions after the differences.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ float dist2_exact(float dx, float dy, float dz) {
 #pragma clang fp contract(off)
   float s = dx * dx;
-  float ty = dy * dy;
-  s = s + ty;
-  float tz = dz * dz;
-  s = s + tz;
+  s = __builtin_fmaf(dy, dy, s);
+  s = __builtin_fmaf(dz, dz, s);
   return s;
 }
 

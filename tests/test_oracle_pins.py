@@ -575,3 +575,41 @@ def test_given_densities_replace_only_the_force_inputs():
     # changes by about eps * rho / (rho - rho0) of its pressure part
     assert 0 < np.abs(c["a_int"] - a["a_int"]).max() < 1e-3 * np.abs(a["a_int"]).max()
     assert np.abs(c["a_coup"] - a["a_coup"]).max() > 0
+
+
+def test_float32_fma_of_the_numpy_oracles_matches_the_c_library():
+    """oracle/fp32.py forms the fused multiply-add of the distance predicate
+    exactly: it agrees bit for bit with the C library's fmaf on random
+    operands, on sums that land on (or one unit beside) a float32 rounding
+    tie, and on cancelling sums."""
+    import ctypes
+
+    from oracle import fp32
+
+    libm = ctypes.CDLL("libm.so.6")
+    libm.fmaf.restype = ctypes.c_float
+    libm.fmaf.argtypes = [ctypes.c_float] * 3
+    rng = np.random.default_rng(31)
+    n = 4000
+    a = rng.uniform(-0.05, 0.05, n).astype(np.float32)
+    cases = [
+        (a, a, rng.uniform(0, 0.01, n).astype(np.float32)),
+        (a, a, (a.astype(np.float64) * a).astype(np.float32)),
+        (a, a, (-(a.astype(np.float64) * a)).astype(np.float32)),
+        # products with 24-bit tails added to values 2^12 larger: the exact sum
+        # sits on a rounding tie or next to it
+        ((rng.integers(-2 ** 12, 2 ** 12, n) * 2.0 ** -12).astype(np.float32),
+         (rng.integers(-2 ** 12, 2 ** 12, n) * 2.0 ** -12).astype(np.float32),
+         (rng.integers(0, 2 ** 20, n) * 2.0 ** -8).astype(np.float32)),
+        (rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32),
+         rng.standard_normal(n).astype(np.float32)),
+    ]
+    for x, y, z in cases:
+        got = fp32.fmaf32(x, y, z)
+        want = np.array([libm.fmaf(float(p), float(q), float(r)) for p, q, r in zip(x, y, z)], np.float32)
+        np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    # the predicate: fused only in the two outer steps
+    dx, dy, dz = (rng.uniform(-0.05, 0.05, n).astype(np.float32) for _ in range(3))
+    want = np.array([libm.fmaf(float(c), float(c), libm.fmaf(float(b), float(b), float(np.float32(a * a))))
+                     for a, b, c in zip(dx, dy, dz)], np.float32)
+    np.testing.assert_array_equal(fp32.dist2(dx, dy, dz).view(np.uint32), want.view(np.uint32))
