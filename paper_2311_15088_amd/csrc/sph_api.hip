@@ -297,7 +297,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->d_scenes, S);
   ar.add(ctx->d_fprefix, S + 1);
   ar.add(ctx->d_aprefix, S + 1);
-  ar.add(ctx->d_pairs, 1);
+  ar.add(ctx->d_pairs, kPairSlots);
   ar.add(ctx->d_tprefix, S + 1);
   ar.add(ctx->d_counters, kWorkCounters);
   ar.add(ctx->d_tile_list, tprefix[S]);
@@ -377,7 +377,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   CHK(hipMemsetAsync(ctx->aoff, 0, 4 * (AC + S), st));
   CHK(hipMemsetAsync(ctx->rho, 0, 4 * std::max<uint64_t>(N, 1), st));
   CHK(hipMemsetAsync(ctx->nbr, 0, 4 * std::max<uint64_t>(N, 1), st));
-  CHK(hipMemsetAsync(ctx->d_pairs, 0, 8, st));
+  CHK(hipMemsetAsync(ctx->d_pairs, 0, 8 * kPairSlots, st));
   CHK(hipMemsetAsync(ctx->d_bar, 0, 8, st));
   CHK(hipMemsetAsync(ctx->d_abort, 0, 4, st));
   if (ctx->diag) {
@@ -820,6 +820,14 @@ int64_t field_bytes(const sph_ctx* ctx, int32_t f) {
   }
 }
 
+// The pair counter's slots summed into one 64-bit word (one wave, fixed order).
+__global__ void k_sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __restrict__ out) {
+  unsigned long long v = 0;
+  for (int k = threadIdx.x; k < kPairSlots; k += kWave) v += slots[k];
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  if (threadIdx.x == 0) *out = v;
+}
+
 sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_bytes) {
   int64_t need = field_bytes(ctx, field);
   if (need < 0) return fail(ctx, SPH_EINVAL, "unknown field %d", field);
@@ -906,7 +914,8 @@ sph_status sph_read_impl(sph_ctx* ctx, int32_t field, void* dst, int64_t dst_byt
       HIPCHK(hipMemcpyAsync(out, ctx->aoff, (size_t)need, hipMemcpyDeviceToDevice, st));
       break;
     case SPH_PAIR_COUNT:
-      HIPCHK(hipMemcpyAsync(out, ctx->d_pairs, 8, hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kWave), 0, st, ctx->d_pairs, (unsigned long long*)out);
+      HIPCHK(hipGetLastError());
       break;
     case SPH_AGENT_FEATURES:
       HIPCHK(hipMemcpyAsync(out, ctx->cplan.feat, (size_t)need, hipMemcpyDeviceToDevice, st));
@@ -983,7 +992,7 @@ static sph_status snapshot(sph_ctx* ctx, Snapshot& sn, bool save) {
     for (void* p : f) sn.parts.push_back({p, 4 * N});
     void* a[] = {ctx->agx, ctx->agy, ctx->agz, ctx->aux, ctx->auy, ctx->auz};
     for (void* p : a) sn.parts.push_back({p, 4 * A});
-    sn.parts.push_back({ctx->d_pairs, 8});
+    sn.parts.push_back({ctx->d_pairs, 8 * kPairSlots});
     sn.parts.push_back({ctx->rho, 4 * N});
     sn.parts.push_back({ctx->nbr, 4 * N});
     sn.parts.push_back({ctx->off, 4 * ((size_t)ctx->C + ctx->nscenes)});

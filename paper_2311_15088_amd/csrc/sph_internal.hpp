@@ -28,8 +28,18 @@ struct SortPlan {
 constexpr int kClStep = 0, kClMode = 1, kClUse = 2, kClCheck = 3, kClChecks = 4, kClFallbacks = 5,
               kClSurrogateSteps = 6, kClExactSteps = 7, kClNeed = 8, kClWords = 9;
 
-constexpr int kWorkCounters = 3;
-constexpr int kCounterDensity = 0, kCounterForce = 1, kCounterList = 2;
+// Work counters of the tiled passes.  Each pass hands its work items out
+// from kItemQueues counters, each on a cache line of its own: queue q holds
+// items q, q + nq, q + 2 nq, ... and serves the workgroups b with b mod nq ==
+// q (nq = min(grid, kItemQueues)); one counter for the whole grid serialised
+// every fetch of every workgroup at one address.
+constexpr int kItemQueues = 8, kQueueStride = 32;  // 32 words = 128 bytes apart
+constexpr int kCounterList = 0;
+constexpr int kCounterDensity = kQueueStride, kCounterForce = kCounterDensity + kItemQueues * kQueueStride;
+constexpr int kWorkCounters = kCounterForce + kItemQueues * kQueueStride;
+// slots of the pair counter (each workgroup adds its count into slot
+// blockIdx mod kPairSlots; a read sums them)
+constexpr int kPairSlots = 64;
 constexpr int kTXMax = 32;  // most cells per fluid tile
 
 // Device arrays of the physics kernels (all scenes concatenated).

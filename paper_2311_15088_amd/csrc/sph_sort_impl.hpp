@@ -88,7 +88,8 @@ __device__ __forceinline__ void scan_reduce_block(const SortSet* __restrict__ se
                                                   uint32_t* __restrict__ bsum, uint32_t* counters, uint32_t blk) {
   __shared__ uint32_t lw[kScanThreads / kWave];
   const uint32_t b = blk;
-  if (b == 0 && threadIdx.x < kWorkCounters && counters) counters[threadIdx.x] = 0u;
+  if (b == 0 && counters)
+    for (int k = threadIdx.x; k < kWorkCounters; k += blockDim.x) counters[k] = 0u;
   const int s = (int)uni(find_set(chunk_prefix, nsets, b));
   const SortSet& S = sets[s];
   const uint32_t c0 = (b - chunk_prefix[s]) * kChunk;
