@@ -10,13 +10,13 @@ density, boid steering + coupling, forces + integration.
 Three regions run the same K steps from the same initial state:
   * timed region: K steps launched directly on the library's stream, with
     HIP events only at the density and force kernels' own start and end (the
-    whole-step time, `value`, and the dominant kernel's duration for the
-    roofline come from this region);
+    kernel durations of the roofline come from this region; its step time is
+    reported as ms_per_step_direct_launches);
   * phase region: the same K steps with an event between every two phases
     as well (the per-phase breakdown; the extra events cost some time
     between launches, so its step time is reported but not used);
-  * graph region: K steps replayed from captured HIP graphs, without events
-    (reported beside).
+  * graph region: K steps replayed from captured HIP graphs, without events:
+    the step time and `value` (with --no-graph, the timed region's).
 
 `roofline` is that of the longer fluid pass of the timed region: its
 algorithmic bytes per launch (18 B per particle for density, 52 B for force +
@@ -481,6 +481,9 @@ def main():
                          "for profiler counter passes")
     ap.add_argument("--tuning", default="", metavar="FUSED,VARIANT,TILE_X",
                     help="execution form for --plain-steps (default: the library's)")
+    ap.add_argument("--plain-workload", default="c1", choices=("c1", "c2", "c3", "c4"),
+                    help="workload of --plain-steps: c1 the 1M dam break, c2 the 16.7M two-block scene, "
+                         "c3 the 512 batched scenes (autotuned first), c4 the 4.2M / 65,536-agent scene")
     args = ap.parse_args()
     if args.copy_kernel:
         import torch
@@ -507,7 +510,15 @@ def main():
     torch.cuda.set_device(0)
     sc = scenes.config1()
     if args.plain_steps:
-        sim = sph.create(sc)
+        if args.plain_workload == "c3":
+            scs = scenes.batched(args.scenes)
+            sim = sph.create_batch(scs)
+            if not args.tuning:
+                log(f"[bench] batched plain steps: {len(scs)} scenes, autotuned {sim.autotune(2)}")
+        else:
+            if args.plain_workload != "c1":
+                sc = scenes.config2() if args.plain_workload == "c2" else scenes.config4()
+            sim = sph.create(sc)
         if args.tuning:
             sim.set_tuning(*[int(t) for t in args.tuning.split(",")])
         if args.search_mode:
@@ -582,7 +593,12 @@ def main():
         log(f"[bench] graph region: {graph_ms:.4f} ms/step")
 
     n, cells, agents = sc.n, info["cells"], sc.n_agents
-    value = K * n / wall
+    # the whole job's rate: K steps replayed from captured graphs (the form a
+    # caller stepping repeatedly uses), else the directly launched region
+    direct_ms = ms_per_step
+    if graph_ms is not None:
+        ms_per_step = graph_ms
+    value = K * n / (ms_per_step * 1e-3 * K)
     # whole-step HBM fraction with B_alg = 154 + 24 C/N bytes per particle-step
     b_alg = 154.0 + 24.0 * cells / n
     hbm_frac_step = b_alg * n / (ms_per_step * 1e-3) / (PEAK_HBM_GBS * 1e9)
@@ -604,6 +620,7 @@ def main():
         "steps": K,
         "warmup": W,
         "ms_per_step": ms_per_step,
+        "ms_per_step_direct_launches": direct_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -624,7 +641,7 @@ def main():
                              for k in B_ALG_PASS},
         "step_hbm_frac": hbm_frac_step,
         "b_alg_bytes_per_particle_step": b_alg,
-        "pair_interactions_per_s": pairs / wall,
+        "pair_interactions_per_s": pairs / (ms_per_step * 1e-3 * K),
         "mean_neighbours": pairs / (K * n),
         "kernel_us_per_step": {k: 1e3 * vms / K for k, vms in kernel_ms.items()},
         "phase_region": {"ms_per_step": phase_wall_ms,
