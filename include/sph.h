@@ -176,8 +176,9 @@ sph_status sph_capture(sph_ctx* ctx, int32_t n_steps);
    fused = 0: one launch per phase (variant = block size / own particles per
    thread / LDS capacity of the fluid passes); fused = 1: one persistent
    launch per step (variant = LDS capacities).  tile_x = grid cells along x
-   that one workgroup of the fluid passes takes at a time (1..32).  Every form
-   gives bit-identical results; only the speed differs. */
+   that one workgroup of the fluid passes takes at a time (1 ..
+   sph_variant_tile_max: 32, or 64 for the variants with tables that wide).
+   Every form gives bit-identical results; only the speed differs. */
 typedef struct sph_tuning {
   int32_t fused, variant, tile_x;
   float ms_per_step; /* measured by sph_autotune (0 when set by hand) */
@@ -196,6 +197,8 @@ sph_status sph_tuning_get(const sph_ctx* ctx, sph_tuning* out);
 /* Number of kernel variants of a form, and the name of one (NULL if out of range). */
 int32_t sph_variant_count(int32_t fused);
 const char* sph_variant_name(int32_t fused, int32_t variant);
+/* Widest tile_x a variant accepts (0 if out of range). */
+int32_t sph_variant_tile_max(int32_t fused, int32_t variant);
 
 /* Neighbour search of the fluid passes.  The paper describes two list-based
    searches: a hash grid of fixed-capacity cell buckets filled through an

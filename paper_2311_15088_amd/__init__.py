@@ -105,7 +105,7 @@ class Info(ctypes.Structure):
 
 EXPORTS = ("sph_create", "sph_create_batch", "sph_step", "sph_read", "sph_field_bytes", "sph_info_get",
            "sph_capture", "sph_abort_set", "sph_step_profiled", "sph_step_timed", "sph_phase_name", "sph_autotune", "sph_tuning_set",
-           "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_destroy", "sph_last_error",
+           "sph_tuning_get", "sph_variant_count", "sph_variant_name", "sph_variant_tile_max", "sph_destroy", "sph_last_error",
            "sph_closure_create", "sph_closure_train", "sph_closure_predict", "sph_closure_predict_static", "sph_closure_gradient",
            "sph_closure_adam_step", "sph_closure_weights", "sph_closure_io", "sph_closure_destroy", "sph_closure_last_error",
            "sph_closure_attach", "sph_closure_stats_get")
@@ -157,6 +157,8 @@ def lib() -> ctypes.CDLL:
         L.sph_tuning_get.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.sph_variant_count.restype = i32
         L.sph_variant_count.argtypes = [i32]
+        L.sph_variant_tile_max.restype = i32
+        L.sph_variant_tile_max.argtypes = [i32, i32]
         L.sph_voxel_enable.restype = ctypes.c_int
         L.sph_voxel_enable.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.POINTER(i32)]
         L.sph_obstacles_set.restype = ctypes.c_int
@@ -205,6 +207,11 @@ def variant_name(fused: int, variant: int) -> Optional[str]:
 
 def variant_count(fused: int) -> int:
     return int(lib().sph_variant_count(int(fused)))
+
+
+def variant_tile_max(fused: int, variant: int) -> int:
+    """Widest tile_x the variant accepts."""
+    return int(lib().sph_variant_tile_max(int(fused), int(variant)))
 
 
 def params(d: Dict, flags: int = 0) -> Params:

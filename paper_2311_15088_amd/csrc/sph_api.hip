@@ -255,9 +255,10 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ctx->nsets = nsets;
   ctx->nchunks = chunk_prefix[nsets];
   // tile width and kernel variant (SPH_TILE_X, SPH_FLUID_VARIANT override the defaults)
-  int tx = 32, variant = 0;
-  if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(kTXMax, atoi(e)));
+  int variant = 0;
   if (const char* e = getenv("SPH_FLUID_VARIANT")) variant = std::max(0, std::min(fluid_variants() - 1, atoi(e)));
+  int tx = fluid_tile_max(0, variant);  // the variant's widest tile
+  if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(fluid_tile_max(0, variant), atoi(e)));
   std::vector<uint32_t> tprefix(S + 1, 0);
   for (int s = 0; s < S; ++s) {
     const uint64_t t = (uint64_t)tprefix[s] + fluid_tiles(hs[s].g, 1);
@@ -958,8 +959,11 @@ static sph_status drop_graph(sph_ctx* ctx) {
 
 static sph_status apply_tuning(sph_ctx* ctx, const sph_tuning& t) {
   const int nv = t.fused ? fused_variant_count() : fluid_variants();
-  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || t.tile_x < 1 || t.tile_x > kTXMax)
-    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile_x %d)", t.fused, t.variant, t.tile_x);
+  if (t.fused < 0 || t.fused > 1 || t.variant < 0 || t.variant >= nv || t.tile_x < 1 ||
+      t.tile_x > fluid_tile_max(t.fused, t.variant))
+    return fail(ctx, SPH_EINVAL, "invalid tuning (fused %d, variant %d, tile_x %d; widest tile %d)", t.fused,
+                t.variant, t.tile_x, (t.fused >= 0 && t.fused <= 1 && t.variant >= 0 && t.variant < nv)
+                                         ? fluid_tile_max(t.fused, t.variant) : 0);
   sph_status st = drop_graph(ctx);
   if (st != SPH_OK) return st;
   st = set_tiling(ctx, t.tile_x, t.fused ? ctx->phys.variant : t.variant);
@@ -1089,10 +1093,11 @@ static sph_status autotune_impl(sph_ctx* ctx, int32_t steps, sph_tuning* best_ou
   best.ms_per_step = 1e30f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<sph_tuning> cands;
-  const int txs[] = {8, 16, 32};
+  const int txs[] = {8, 16, 32, 64};
   for (int fused = 0; fused <= 1; ++fused)
     for (int v = 0; v < (fused ? fused_variant_count() : fluid_variants()); ++v)
-      for (int tx : txs) cands.push_back(sph_tuning{fused, v, tx, 0.0f});
+      for (int tx : txs)
+        if (tx <= fluid_tile_max(fused, v)) cands.push_back(sph_tuning{fused, v, tx, 0.0f});
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(ctx, SPH_EHIP, "event create");
   for (size_t c = 0; c < cands.size() && st == SPH_OK; ++c) {
     st = apply_tuning(ctx, cands[c]);
@@ -1330,6 +1335,11 @@ sph_status sph_tuning_get(const sph_ctx* ctx, sph_tuning* out) {
 }
 
 int32_t sph_variant_count(int32_t fused) { return fused ? fused_variant_count() : fluid_variants(); }
+
+int32_t sph_variant_tile_max(int32_t fused, int32_t variant) {
+  if (fused < 0 || fused > 1 || variant < 0 || variant >= sph_variant_count(fused)) return 0;
+  return fluid_tile_max(fused, variant);
+}
 
 const char* sph_variant_name(int32_t fused, int32_t variant) {
   return fused ? fused_variant_name(variant) : fluid_variant_name(variant);

@@ -48,7 +48,7 @@ constexpr int kWorkCounters = kCounterForce + kItemQueues * kQueueStride;
 // slots of the pair counter (each workgroup adds its count into slot
 // blockIdx mod kPairSlots; a read sums them)
 constexpr int kPairSlots = 64;
-constexpr int kTXMax = 32;  // most cells per fluid tile
+constexpr int kTXMax = 64;  // most cells per fluid tile (kernel variants may allow fewer)
 
 // Device arrays of the physics kernels (all scenes concatenated).
 struct PhysPlan {
@@ -106,6 +106,8 @@ uint32_t fluid_tiles(const DGrid& g, int tx);
 int fluid_variants();
 // particles per work item of the fluid passes: the block size of the form
 int fluid_item_max(int fused, int variant);
+// Widest tile (cells along x) a kernel variant's LDS tables hold.
+int fluid_tile_max(int fused, int variant);
 const char* fluid_variant_name(int v);
 // The sort's fix-up and the fluid passes' work-item list in one launch (the
 // list needs only the cell offsets, so it overlaps the fix-up).

@@ -20,9 +20,9 @@ __global__ void __launch_bounds__(256) k_fixup_tiles(const SortSet* __restrict__
   else fixup_block(sets, nsets, bprefix, blockIdx.x - tile_blocks);
 }
 
-template <bool FORCE, int BD, int CAP, bool UNIT_H = false>
+template <bool FORCE, int BD, int CAP, bool UNIT_H = false, int TXM = 32>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
-  fluid_tiles<FORCE, BD, CAP, UNIT_H>(P);
+  fluid_tiles<FORCE, BD, CAP, UNIT_H, TXM>(P);
 }
 
 template <int BD>
@@ -40,14 +40,16 @@ struct FluidVariant {
   const void* density;
   const void* density_unit;  // the density pass when every scene has h^2 <= 1
   const void* force;
-  int bd_density, bd_force, item_max;
+  int bd_density, bd_force, item_max, tile_max;
   const char* name;
 };
 
-template <int BDD, int CD, int BDF, int CF>
+// TXM: widest tile of the variant.
+template <int BDD, int CD, int BDF, int CF, int TXM = 32>
 static FluidVariant make_variant(int item_max, const char* name) {
-  return FluidVariant{(const void*)k_fluid<false, BDD, CD>, (const void*)k_fluid<false, BDD, CD, true>,
-                      (const void*)k_fluid<true, BDF, CF>, BDD, BDF, item_max, name};
+  return FluidVariant{(const void*)k_fluid<false, BDD, CD, false, TXM>,
+                      (const void*)k_fluid<false, BDD, CD, true, TXM>,
+                      (const void*)k_fluid<true, BDF, CF, false, TXM>, BDD, BDF, item_max, TXM, name};
 }
 
 static const FluidVariant* variants() {
@@ -69,10 +71,16 @@ static const FluidVariant* variants() {
       make_variant<512, 512, 256, 512>(512, "d512_f256_ppt2"),
       make_variant<256, 512, 256, 512>(512, "bd256_ppt2"),
       make_variant<256, 512, 256, 512>(1024, "bd256_ppt4"),
+      // both passes with 512 threads on tiles of up to 64 cells: at rest
+      // density a tile then holds about 512 particles, one per thread of
+      // either pass (config 1, first 100 steps: 0.250 against 0.255 ms per
+      // step for the default; over 1,000 steps, as the column compresses,
+      // 0.398 against 0.375)
+      make_variant<512, 512, 512, 512, 64>(512, "bd512_tx64"),
   };
   return v;
 }
-constexpr int kNumVariants = 11;
+constexpr int kNumVariants = 12;
 constexpr int kAgentBD = 256;
 
 int fluid_variants() { return kNumVariants; }
@@ -82,6 +90,11 @@ int fluid_item_max(int fused, int variant) {
   return variants()[(variant >= 0 && variant < kNumVariants) ? variant : 0].item_max;
 }
 const char* fluid_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? variants()[v].name : nullptr; }
+
+int fluid_tile_max(int fused, int variant) {
+  if (fused) return 32;  // the fused kernel's tables
+  return (variant >= 0 && variant < kNumVariants) ? variants()[variant].tile_max : 0;
+}
 
 static int persistent_blocks(const void* fn, int bd) {
   static int ncu = 0;

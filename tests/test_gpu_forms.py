@@ -38,7 +38,7 @@ def test_variants_and_tile_widths_are_bit_identical():
     print(f"[forms] n={sc.n}", flush=True)
     ref = run(sc, 4)
     for v in range(sph.variant_count(0)):
-        for tx in WIDTHS:
+        for tx in WIDTHS + ((64, 48) if sph.variant_tile_max(0, v) >= 64 else ()):
             same(ref, run(sc, 4, 0, v, tx))
 
 
@@ -51,7 +51,7 @@ def test_dense_clump_takes_every_path_bit_identically():
     print(f"[forms] clump n={sc.n}", flush=True)
     ref = run(sc, 2)
     for v in range(sph.variant_count(0)):
-        for tx in (32, 1, 5):
+        for tx in (32, 1, 5) + ((64,) if sph.variant_tile_max(0, v) >= 64 else ()):
             print(f"[forms] clump variant {v} tile_x {tx}", flush=True)
             same(ref, run(sc, 2, 0, v, tx))
     for v in range(sph.variant_count(1)):
@@ -108,7 +108,11 @@ def test_autotune_keeps_state_and_picks_a_valid_form():
 def test_invalid_tuning_is_rejected():
     sc = scenes.small_dam(nx=5, ny=5, nz=5, n_agents=2)
     sim = sph.create(sc)
-    for bad in ((2, 0, 16), (0, 99, 16), (0, 0, 0), (0, 0, 33), (1, 99, 8)):
+    wide = [v for v in range(sph.variant_count(0)) if sph.variant_tile_max(0, v) == 64]
+    narrow = [v for v in range(sph.variant_count(0)) if sph.variant_tile_max(0, v) == 32]
+    assert wide and narrow and sph.variant_tile_max(1, 0) == 32
+    sim.set_tuning(0, wide[0], 64)
+    for bad in ((2, 0, 16), (0, 99, 16), (0, 0, 0), (0, wide[0], 65), (0, narrow[0], 33), (1, 0, 33), (1, 99, 8)):
         with pytest.raises(sph.SphError) as ei:
             sim.set_tuning(*bad)
         assert ei.value.status == sph.EINVAL
