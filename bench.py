@@ -71,8 +71,14 @@ B_ALG_PASS = {"density": 18, "force_integrate": 52}
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for a
 # plain device copy of known size), averaged over the timed steps of the run
 # named; valid only for the kernel sources it was measured on.
-TRAFFIC = {}
-FLUID_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip")
+TRAFFIC = {
+    "density": {"sources_sha256_16": "9541843fc9ca6ed3", "bytes_per_launch": 92.4e6,
+                "run": "bench.py --plain-steps 25, dispatches 6-25 (profiles/fluid_counters_dam_break_1M.md)"},
+    "force_integrate": {"sources_sha256_16": "9541843fc9ca6ed3", "bytes_per_launch": 182.1e6,
+                        "run": "bench.py --plain-steps 25, dispatches 6-25 (profiles/fluid_counters_dam_break_1M.md)"},
+}
+FLUID_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip",
+                 "paper_2311_15088_amd/csrc/sph_internal.hpp", "paper_2311_15088_amd/csrc/sph_device.hpp")
 
 
 def sources_hash():
