@@ -277,7 +277,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ar.add(ctx->sx, N); ar.add(ctx->sy, N); ar.add(ctx->sz, N);
   ar.add(ctx->svx, N); ar.add(ctx->svy, N); ar.add(ctx->svz, N);
   ar.add(ctx->sid, N); ar.add(ctx->key, N); ar.add(ctx->rank, N); ar.add(ctx->tsrc, N); ar.add(ctx->tid, N);
-  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * 6 * N);
+  ar.add(ctx->rho, N); ar.add(ctx->nbr, N); ar.add(ctx->nmask, 9 * 6 * N); ar.add(ctx->rowcode, N);
   ar.add(ctx->cnt, C); ar.add(ctx->off, C + S);
   ar.add(ctx->agx, A); ar.add(ctx->agy, A); ar.add(ctx->agz, A);
   ar.add(ctx->aux, A); ar.add(ctx->auy, A); ar.add(ctx->auz, A);
@@ -452,6 +452,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   P.rho = ctx->rho;
   P.nbr = ctx->nbr;
   P.nmask = ctx->nmask;
+  P.rowcode = ctx->rowcode;
   P.pairs = ctx->d_pairs;
   P.tprefix = ctx->d_tprefix;
   P.ntiles = tprefix[S];

@@ -33,6 +33,7 @@ struct sph_ctx {
   float* rho;
   uint32_t* nbr;
   uint32_t* nmask;
+  uint32_t* rowcode;
   uint32_t *cnt, *off;
   // agents: state (id order), cell-ordered copies, scratch
   float *agx, *agy, *agz, *aux, *auy, *auz;

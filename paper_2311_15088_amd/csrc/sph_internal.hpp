@@ -64,6 +64,7 @@ struct PhysPlan {
   float* rho;
   uint32_t* nbr;
   uint32_t* nmask;             // [9][6][nf] neighbours among each halo row's candidates, 32 per word (density -> force)
+  uint32_t* rowcode;           // [nf] each halo row's candidate cells, 3 bits per row (density -> force)
   unsigned long long* pairs;   // running sum of neighbour counts
   // tiles: runs of tx cells along x in one grid row (all scenes concatenated)
   const uint32_t* tprefix;     // [nscenes + 1] tile prefix
