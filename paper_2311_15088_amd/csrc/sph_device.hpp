@@ -70,6 +70,14 @@ __device__ __forceinline__ float dist2_exact(float dx, float dy, float dz) {
   return s;
 }
 
+// A product rounded on its own, never fused into the add that uses it: the
+// force passes scale C_p k h (rho - rho0) and C_v mu v once per particle or
+// per staged candidate, and every form must round them alike.
+__device__ __forceinline__ float mul_rn(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 __device__ __forceinline__ int cell_coord(float p, float mn, float inv, int dim) {
 #pragma clang fp contract(off)
   float t = p - mn;

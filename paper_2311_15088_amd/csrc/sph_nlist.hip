@@ -239,6 +239,8 @@ __global__ void __launch_bounds__(kListBD) k_list_force(PhysPlan P, ListPlan L) 
   const float vxi = P.svx[i], vyi = P.svy[i], vzi = P.svz[i];
   const float di = P.rho[i] - S.rho0;
   const float inv_h = S.inv_h, cpk_h = S.cpk_h, cvmu = S.cvmu;
+  // scaled as in the tiled force pass, so that both forms give the same sums
+  const float ci = mul_rn(cpk_h, di), cvx = mul_rn(cvmu, vxi), cvy = mul_rn(cvmu, vyi), cvz = mul_rn(cvmu, vzi);
   const uint64_t start = list_start(L, i);
   const uint32_t m = list_len(L, start, L.lcnt[i]);
   const uint32_t* __restrict__ lst = L.list + start;
@@ -248,16 +250,17 @@ __global__ void __launch_bounds__(kListBD) k_list_force(PhysPlan P, ListPlan L) 
     const float dx = P.sx[j] - xi, dy = P.sy[j] - yi, dz = P.sz[j] - zi;
     const float r2 = dist2_exact(dx, dy, dz);
     if (r2 > 0.0f) {
-      // (m/rho_j) w [Cp k h (d_i + d_j) w / r * r_ij - Cv mu v_ij],  r_ij = -(dx, dy, dz)
+      // (m/rho_j) w [(Cp k h d_i + Cp k h d_j) w / r * r_ij - (Cv mu v_i - Cv mu v_j)],
+      // r_ij = -(dx, dy, dz)
       const float rhoj = P.rho[j];
-      const float mr = S.m * __builtin_amdgcn_rcpf(rhoj), dj = rhoj - S.rho0;
+      const float mr = S.m * __builtin_amdgcn_rcpf(rhoj), pj = mul_rn(cpk_h, rhoj - S.rho0);
       const float ir = rsqrt_normal(r2);
       const float w = 1.0f - r2 * ir * inv_h;
       const float sc = mr * w;
-      const float fp = cpk_h * (di + dj) * w * ir;
-      acc0 += sc * (-fp * dx - cvmu * (vxi - P.svx[j]));
-      acc1 += sc * (-fp * dy - cvmu * (vyi - P.svy[j]));
-      acc2 += sc * (-fp * dz - cvmu * (vzi - P.svz[j]));
+      const float fp = (ci + pj) * w * ir;
+      acc0 += sc * (-fp * dx - (cvx - mul_rn(cvmu, P.svx[j])));
+      acc1 += sc * (-fp * dy - (cvy - mul_rn(cvmu, P.svy[j])));
+      acc2 += sc * (-fp * dz - (cvz - mul_rn(cvmu, P.svz[j])));
     }
   }
   const float irho = __builtin_amdgcn_rcpf(di + S.rho0);
