@@ -72,10 +72,10 @@ B_ALG_PASS = {"density": 18, "force_integrate": 52}
 # plain device copy of known size), averaged over the timed steps of the run
 # named; valid only for the kernel sources it was measured on.
 TRAFFIC = {
-    "density": {"sources_sha256_16": "9541843fc9ca6ed3", "bytes_per_launch": 92.4e6,
-                "run": "bench.py --plain-steps 25, dispatches 6-25 (profiles/fluid_counters_dam_break_1M.md)"},
-    "force_integrate": {"sources_sha256_16": "9541843fc9ca6ed3", "bytes_per_launch": 182.1e6,
-                        "run": "bench.py --plain-steps 25, dispatches 6-25 (profiles/fluid_counters_dam_break_1M.md)"},
+    "density": {"sources_sha256_16": "51dc334470b55ab7", "bytes_per_launch": 103.5e6,
+                "run": "bench.py --plain-steps 1025, dispatches 26-1025 (profiles/fluid_counters_dam_break_1M.md)"},
+    "force_integrate": {"sources_sha256_16": "51dc334470b55ab7", "bytes_per_launch": 194.3e6,
+                        "run": "bench.py --plain-steps 1025, dispatches 26-1025 (profiles/fluid_counters_dam_break_1M.md)"},
 }
 FLUID_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip",
                  "paper_2311_15088_amd/csrc/sph_internal.hpp", "paper_2311_15088_amd/csrc/sph_device.hpp")
