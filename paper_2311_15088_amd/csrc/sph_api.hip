@@ -459,7 +459,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   P.tile_list = ctx->d_tile_list;
   P.tx = tx;
   P.variant = variant;
-  if (set_tiling(ctx, tx, variant) != SPH_OK) return bail(SPH_EHIP);
+  if (set_tiling(ctx, tx, variant, ctx->fused) != SPH_OK) return bail(SPH_EHIP);
   P.item_max = (uint32_t)fluid_item_max(ctx->fused ? 1 : 0, ctx->fused ? ctx->fused_variant : variant);
   if (ctx->features && sph_ctx_closure_buffers(ctx) != SPH_OK) return bail(SPH_ENOMEM);
   P.counters = ctx->d_counters;
@@ -480,19 +480,22 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   return SPH_OK;
 }
 
-// Tile width and kernel variant of the fluid passes.  The tile list is sized
-// for one-cell tiles, so any width fits.
-sph_status set_tiling(sph_ctx* ctx, int tx, int variant) {
+// Tile width and kernel variant of the fluid passes; the tile extent along y
+// is the variant's (one row in the fused step, whose kernel stages nine halo
+// rows).  The tile list is sized for one-cell tiles, so any shape fits.
+sph_status set_tiling(sph_ctx* ctx, int tx, int variant, bool fused) {
   if (tx < 1 || tx > kTXMax || variant < 0 || variant >= fluid_variants())
     return fail(ctx, SPH_EINVAL, "tile width must be in [1, %d] and variant in [0, %d)", kTXMax, fluid_variants());
+  const int ty = fluid_tile_y(fused ? 1 : 0, variant);
   std::vector<uint32_t> tp(ctx->nscenes + 1, 0);
-  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx);
+  for (int s = 0; s < ctx->nscenes; ++s) tp[s + 1] = tp[s] + fluid_tiles(ctx->hs[s].g, tx, ty);
   // ordered after every kernel already enqueued on the stream that reads the old prefix
   hipError_t e = hipMemcpyAsync(ctx->d_tprefix, tp.data(), 4 * tp.size(), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(ctx, SPH_EHIP, "tile prefix upload: %s", hipGetErrorString(e));
   ctx->phys.ntiles = tp[ctx->nscenes];
   ctx->phys.tx = tx;
+  ctx->phys.ty = ty;
   ctx->phys.variant = variant;
   return SPH_OK;
 }
@@ -967,7 +970,7 @@ static sph_status apply_tuning(sph_ctx* ctx, const sph_tuning& t) {
                                          ? fluid_tile_max(t.fused, t.variant) : 0);
   sph_status st = drop_graph(ctx);
   if (st != SPH_OK) return st;
-  st = set_tiling(ctx, t.tile_x, t.fused ? ctx->phys.variant : t.variant);
+  st = set_tiling(ctx, t.tile_x, t.fused ? ctx->phys.variant : t.variant, t.fused != 0);
   if (st != SPH_OK) return st;
   ctx->fused = t.fused != 0;
   if (t.fused) ctx->fused_variant = t.variant;

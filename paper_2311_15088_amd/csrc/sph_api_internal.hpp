@@ -98,7 +98,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
                          const std::vector<const float*>& vel, const std::vector<const float*>& apos,
                          const std::vector<const float*>& avel, void* stream, sph_ctx** out);
 sph_status sph_enqueue_steps(sph_ctx* ctx, int32_t n_steps, hipStream_t st);
-sph_status set_tiling(sph_ctx* ctx, int tx, int variant);
+sph_status set_tiling(sph_ctx* ctx, int tx, int variant, bool fused);
 sph_status sph_ctx_closure_buffers(sph_ctx* ctx);
 void sph_ctx_closure_phase(sph_ctx* ctx, hipStream_t st);
 void sph_ctx_closure_end(sph_ctx* ctx, hipStream_t st);

@@ -462,7 +462,14 @@ sph_status sph_closure_attach(sph_ctx* ctx, sph_closure* cl, int32_t check_every
   ctx->phys.cl_fhat = ctx->cplan.fhat;
   ctx->phys.cl_state = ctx->cplan.state;
   ctx->phys.cl_err = ctx->cplan.err;
-  ctx->fused = false;  // the closure runs between phases of a step
+  if (ctx->fused) {
+    // the closure runs between phases of a step: back to per-phase launches
+    // of the context's kernel variant, with that variant's tiles
+    const sph_status t = set_tiling(ctx, ctx->phys.tx, ctx->phys.variant, false);
+    if (t != SPH_OK) return t;
+    ctx->fused = false;
+    ctx->phys.item_max = (uint32_t)fluid_item_max(0, ctx->phys.variant);
+  }
   return SPH_OK;
 }
 

@@ -70,6 +70,7 @@ struct PhysPlan {
   const uint32_t* tprefix;     // [nscenes + 1] tile prefix
   uint32_t ntiles;
   int tx;                      // cells per tile along x (<= kTXMax)
+  int ty;                      // grid rows per tile along y (the kernel variant's; 1 in the fused step)
   int variant;                 // kernel variant (block size, particles per thread, LDS capacity)
   int unit_h;                  // every scene has h^2 <= 1 (a density-pass form relies on it)
   unsigned long long* tile_list;  // [cells] work items of this step (tile << 16 | first cell << 8 | last cell)
@@ -103,12 +104,14 @@ uint32_t scan_chunks(uint32_t ncells);
 
 // fix-up + work-item list, density, agents, force + integration
 constexpr int kStepPhases = kSortPhases + 3;
-uint32_t fluid_tiles(const DGrid& g, int tx);
+uint32_t fluid_tiles(const DGrid& g, int tx, int ty = 1);
 int fluid_variants();
 // particles per work item of the fluid passes: the block size of the form
 int fluid_item_max(int fused, int variant);
 // Widest tile (cells along x) a kernel variant's LDS tables hold.
 int fluid_tile_max(int fused, int variant);
+// Grid rows per tile along y of a kernel variant (1 for the fused step).
+int fluid_tile_y(int fused, int variant);
 const char* fluid_variant_name(int v);
 // The sort's fix-up and the fluid passes' work-item list in one launch (the
 // list needs only the cell offsets, so it overlaps the fix-up).

@@ -20,9 +20,9 @@ __global__ void __launch_bounds__(256) k_fixup_tiles(const SortSet* __restrict__
   else fixup_block(sets, nsets, bprefix, blockIdx.x - tile_blocks);
 }
 
-template <bool FORCE, int BD, int CAP, bool UNIT_H = false, int TXM = 32>
+template <bool FORCE, int BD, int CAP, bool UNIT_H = false, int TXM = 32, int TY = 1>
 __global__ void __launch_bounds__(BD) k_fluid(PhysPlan P) {
-  fluid_tiles<FORCE, BD, CAP, UNIT_H, TXM>(P);
+  fluid_tiles<FORCE, BD, CAP, UNIT_H, TXM, TY>(P);
 }
 
 template <int BD>
@@ -40,16 +40,16 @@ struct FluidVariant {
   const void* density;
   const void* density_unit;  // the density pass when every scene has h^2 <= 1
   const void* force;
-  int bd_density, bd_force, item_max, tile_max;
+  int bd_density, bd_force, item_max, tile_max, tile_y;
   const char* name;
 };
 
-// TXM: widest tile of the variant.
-template <int BDD, int CD, int BDF, int CF, int TXM = 32>
+// TXM: widest tile of the variant; TY: its grid rows per tile along y.
+template <int BDD, int CD, int BDF, int CF, int TXM = 32, int TY = 1>
 static FluidVariant make_variant(int item_max, const char* name) {
-  return FluidVariant{(const void*)k_fluid<false, BDD, CD, false, TXM>,
-                      (const void*)k_fluid<false, BDD, CD, true, TXM>,
-                      (const void*)k_fluid<true, BDF, CF, false, TXM>, BDD, BDF, item_max, TXM, name};
+  return FluidVariant{(const void*)k_fluid<false, BDD, CD, false, TXM, TY>,
+                      (const void*)k_fluid<false, BDD, CD, true, TXM, TY>,
+                      (const void*)k_fluid<true, BDF, CF, false, TXM, TY>, BDD, BDF, item_max, TXM, TY, name};
 }
 
 static const FluidVariant* variants() {
@@ -77,10 +77,16 @@ static const FluidVariant* variants() {
       // step for the default; over 1,000 steps, as the column compresses,
       // 0.398 against 0.375)
       make_variant<512, 512, 512, 512, 64>(512, "bd512_tx64"),
+      // tiles of two grid rows along y: twelve halo rows staged for two
+      // rows of own particles instead of nine per row (a third fewer
+      // stagings per own particle); each lane skips the three rows outside
+      // its own stencil
+      make_variant<512, 512, 256, 512, 32, 2>(256, "d512_f256_ty2"),
+      make_variant<512, 512, 512, 512, 32, 2>(512, "bd512_ty2"),
   };
   return v;
 }
-constexpr int kNumVariants = 12;
+constexpr int kNumVariants = 14;
 constexpr int kAgentBD = 256;
 
 int fluid_variants() { return kNumVariants; }
@@ -90,6 +96,11 @@ int fluid_item_max(int fused, int variant) {
   return variants()[(variant >= 0 && variant < kNumVariants) ? variant : 0].item_max;
 }
 const char* fluid_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? variants()[v].name : nullptr; }
+
+int fluid_tile_y(int fused, int variant) {
+  if (fused) return 1;
+  return (variant >= 0 && variant < kNumVariants) ? variants()[variant].tile_y : 1;
+}
 
 int fluid_tile_max(int fused, int variant) {
   if (fused) return 32;  // the fused kernel's tables
@@ -149,6 +160,6 @@ void launch_agents(const PhysPlan& P, hipStream_t st) {
                      P);
 }
 
-uint32_t fluid_tiles(const DGrid& g, int tx) { return tiles_of(g, tx); }
+uint32_t fluid_tiles(const DGrid& g, int tx, int ty) { return tiles_of(g, tx, ty); }
 
 }  // namespace sph
