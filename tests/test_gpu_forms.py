@@ -87,6 +87,56 @@ def test_fused_batched_matches_plain_per_scene():
     bat.close()
 
 
+def test_two_row_tiles_batched_equal_plain_per_scene():
+    """Two-row tiles over batched scenes of different grids (odd and even
+    row counts along y, so some tiles hold one row): each scene's result is
+    the plain one-scene step's, bit for bit."""
+    specs = scenes.batched_specs(5, n_range=(300, 4000), a_range=(2, 40))
+    scs = [scenes.batched_scene(sp, k) for k, sp in enumerate(specs)]
+    two_row = [v for v in range(sph.variant_count(0)) if "ty2" in (sph.variant_name(0, v) or "")]
+    assert two_row
+    plain = [run(sc, 3) for sc in scs]
+    for v in two_row:
+        print(f"[forms] batched two-row variant {v}", flush=True)
+        bat = sph.create_batch(scs)
+        bat.set_tuning(0, v, 16)
+        bat.step(3)
+        X, V, Y, U = (bat.read(f) for f in (sph.POS, sph.VEL, sph.AGENT_POS, sph.AGENT_VEL))
+        for s in range(len(scs)):
+            x, vv, y, u, _, _ = plain[s]
+            p0, p1 = bat.part_off[s], bat.part_off[s + 1]
+            a0, a1 = bat.agent_off[s], bat.agent_off[s + 1]
+            np.testing.assert_array_equal(X[p0:p1], x)
+            np.testing.assert_array_equal(V[p0:p1], vv)
+            np.testing.assert_array_equal(Y[a0:a1], y)
+            np.testing.assert_array_equal(U[a0:a1], u)
+        bat.close()
+
+
+def test_closure_attached_to_a_fused_context_steps_per_phase():
+    """Attaching a closure turns a fused context back to per-phase launches
+    with its kernel variant's tiles (here a two-row variant); with a bound of
+    0 the controller always takes the exact gather, so the steps equal plain
+    ones."""
+    sc = scenes.config0c()
+    v2 = [v for v in range(sph.variant_count(0)) if "ty2" in (sph.variant_name(0, v) or "")][0]
+    a = sph.create(sc)
+    a.set_tuning(0, v2, 16)
+    a.set_tuning(1, 0, 16)  # fused; the per-phase variant stays the two-row one
+    a.step(1)
+    cl = sph.Closure(scenes.mlp_flat(scenes.mlp_init()))
+    a.attach_closure(cl, check_every=2, max_rel_rms=0.0)
+    assert a.tuning()["fused"] == 0
+    a.step(3)
+    b = sph.create(sc)
+    b.step(4)
+    same(state(b), state(a))
+    a.attach_closure(None)
+    a.close()
+    b.close()
+    cl.close()
+
+
 def test_autotune_keeps_state_and_picks_a_valid_form():
     sc = scenes.small_dam(nx=24, ny=10, nz=20, n_agents=40, agents="inside")
     a = sph.create(sc)
