@@ -160,13 +160,20 @@ __device__ __forceinline__ void scatter_block(const SortSet* __restrict__ sets, 
   S.tid[pos] = S.id[li];
 }
 
+// ids staged in LDS per fix-up block: the cells of a block's 256 slots span
+// this many slots at most when no cell holds more than 384 particles
+constexpr uint32_t kFixStage = 1024;
+
 __device__ __forceinline__ void fixup_block(const SortSet* __restrict__ sets, int nsets,
                                                    const uint32_t* __restrict__ bprefix, uint32_t blk) {
+  __shared__ uint32_t s_ids[kFixStage];
+  __shared__ uint32_t s_lo[kSortBD / kWave], s_hi[kSortBD / kWave];
   const int s = (int)uni(find_set(bprefix, nsets, blk));
   const SortSet& S = sets[s];
   const uint32_t first = (blk - bprefix[s]) * kSortBD;
   const uint32_t slot = first + threadIdx.x;
   const uint32_t w0 = first + (threadIdx.x & ~(kWave - 1));  // first slot of this wavefront
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool act = slot < S.n;
   uint32_t src = 0, myid = 0, a = 0, len = 0;
   if (act) {
@@ -176,20 +183,48 @@ __device__ __forceinline__ void fixup_block(const SortSet* __restrict__ sets, in
     a = S.off[c];
     len = S.off[c + 1] - a;
   }
-  // rank = number of ids in the cell smaller than mine; ids of slots inside
-  // this wavefront come from the other lanes, the rest from memory
-  uint32_t maxlen = len;
+  // rank = number of ids in the cell smaller than mine.  The slots of the
+  // cells this block's slots lie in are staged in LDS when they fit (one
+  // coalesced load per slot); otherwise ids of slots inside this wavefront
+  // come from the other lanes and the rest from memory.
+  uint32_t maxlen = len, lo = act ? a : 0xffffffffu, hi = act ? a + len : 0u;
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) maxlen = max(maxlen, (uint32_t)__shfl_xor(maxlen, d));
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    maxlen = max(maxlen, (uint32_t)__shfl_xor(maxlen, d));
+    lo = min(lo, (uint32_t)__shfl_xor(lo, d));
+    hi = max(hi, (uint32_t)__shfl_xor(hi, d));
+  }
+  if (lane == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+  }
+  __syncthreads();
+  uint32_t blo = 0xffffffffu, bhi = 0u;
+#pragma unroll
+  for (int w = 0; w < kSortBD / kWave; ++w) {
+    blo = min(blo, s_lo[w]);
+    bhi = max(bhi, s_hi[w]);
+  }
+  const bool staged = bhi > blo && bhi - blo <= kFixStage;  // the same for the whole block
+  if (staged)
+    for (uint32_t e = threadIdx.x; e < bhi - blo; e += kSortBD) s_ids[e] = S.tid[blo + e];
+  __syncthreads();
   uint32_t r = 0;
-  for (uint32_t k = 0; k < maxlen; ++k) {
-    const uint32_t t = a + k;
-    uint32_t v = (uint32_t)__shfl(myid, (int)((t - w0) & (kWave - 1)));
-    if (k < len) {
-      if (t - w0 >= (uint32_t)kWave) v = S.tid[t];
-      r += (v < myid) ? 1u : 0u;
+  if (staged) {
+    const uint32_t* __restrict__ cell = s_ids + (a - blo);
+    for (uint32_t k = 0; k < maxlen; ++k)
+      if (k < len) r += (cell[k] < myid) ? 1u : 0u;
+  } else {
+    for (uint32_t k = 0; k < maxlen; ++k) {
+      const uint32_t t = a + k;
+      uint32_t v = (uint32_t)__shfl(myid, (int)((t - w0) & (kWave - 1)));
+      if (k < len) {
+        if (t - w0 >= (uint32_t)kWave) v = S.tid[t];
+        r += (v < myid) ? 1u : 0u;
+      }
     }
   }
+  __syncthreads();  // the shared words are reused by the next call
   if (!act) return;
   const uint32_t dst = a + r;
   S.sx[dst] = S.x[src];
