@@ -51,13 +51,31 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
   cell_of(S.g, ya[0], ya[1], ya[2], fx, fy, fz);
   const int ns = S.ns_c, side = 2 * ns + 1, nrows = side * side;
   const int fx0 = max(fx - ns, 0), fx1 = min(fx + ns, S.g.dim[0] - 1);
+  // each row is cut to the cells that can hold a point within r_couple: a
+  // row whose y/z slab lies farther is empty, and in the others only the
+  // cells meeting [x - e, x + e], e = sqrt(r_couple^2 - d_yz^2), are read
+  // (a margin of 10^-3 cells absorbs float32 rounding, so the coupling set is
+  // exactly that of the full stencil)
+  const float gd = S.g.cell, gslack = 1e-3f * gd;
+  const float rcut = sqrtf(S.rc2) * (1.0f + 1e-5f);
   auto fluid_row = [&](int q, uint32_t& r0, uint32_t& r1) {
     r0 = r1 = 0;
     if (q < nrows) {
       const int y = fy + q % side - ns, z = fz + q / side - ns;
       if (y >= 0 && y < S.g.dim[1] && z >= 0 && z < S.g.dim[2]) {
-        r0 = off[hash3(S.g, fx0, y, z)];
-        r1 = off[hash3(S.g, fx1, y, z) + 1];
+        const float ylo = S.g.mn[1] + (float)y * gd, zlo = S.g.mn[2] + (float)z * gd;
+        const float gy = fmaxf(fmaxf(ylo - ya[1], ya[1] - (ylo + gd)) - gslack, 0.0f);
+        const float gz = fmaxf(fmaxf(zlo - ya[2], ya[2] - (zlo + gd)) - gslack, 0.0f);
+        const float q2 = gy * gy + gz * gz;
+        if (q2 < rcut * rcut) {
+          const float e = __builtin_amdgcn_sqrtf(rcut * rcut - q2) + gslack;
+          const int lo = max(fx0, (int)floorf((ya[0] - e - S.g.mn[0]) * S.g.inv));
+          const int hi = min(fx1, (int)floorf((ya[0] + e - S.g.mn[0]) * S.g.inv));
+          if (lo <= hi) {
+            r0 = off[hash3(S.g, lo, y, z)];
+            r1 = off[hash3(S.g, hi, y, z) + 1];
+          }
+        }
       }
     }
   };
