@@ -95,10 +95,24 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
     const int x0 = max(cx - 1, 0), x1 = min(cx + 1, S.ga.dim[0] - 1);
     uint32_t rb0 = 0, rb1 = 0;
     if (lane < 9) {
+      // rows cut to the cells within the widest boid radius, as the fluid rows
       const int y = cy + (lane % 3) - 1, z = cz + (lane / 3) - 1;
       if (y >= 0 && y < S.ga.dim[1] && z >= 0 && z < S.ga.dim[2]) {
-        rb0 = aoff[hash3(S.ga, x0, y, z)];
-        rb1 = aoff[hash3(S.ga, x1, y, z) + 1];
+        const float ad = S.ga.cell, aslack = 1e-3f * ad;
+        const float rmax = sqrtf(rmax2) * (1.0f + 1e-5f);
+        const float ylo = S.ga.mn[1] + (float)y * ad, zlo = S.ga.mn[2] + (float)z * ad;
+        const float gy = fmaxf(fmaxf(ylo - ya[1], ya[1] - (ylo + ad)) - aslack, 0.0f);
+        const float gz = fmaxf(fmaxf(zlo - ya[2], ya[2] - (zlo + ad)) - aslack, 0.0f);
+        const float q2 = gy * gy + gz * gz;
+        if (q2 < rmax * rmax) {
+          const float e = __builtin_amdgcn_sqrtf(rmax * rmax - q2) + aslack;
+          const int lo = max(x0, (int)floorf((ya[0] - e - S.ga.mn[0]) * S.ga.inv));
+          const int hi = min(x1, (int)floorf((ya[0] + e - S.ga.mn[0]) * S.ga.inv));
+          if (lo <= hi) {
+            rb0 = aoff[hash3(S.ga, lo, y, z)];
+            rb1 = aoff[hash3(S.ga, hi, y, z) + 1];
+          }
+        }
       }
     }
     const FlatRows F = flat_rows(s_pre[wave], s_dlt[wave], lane, 9, S.abase + rb0, rb1 - rb0);
