@@ -208,12 +208,19 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
           ok[u] = t < R.total;
           j[u] = ok[u] ? flat_index(R, t, cur) : 0u;
         }
+        // density and velocity are loaded with the position, before the
+        // distance test: after the row pruning about half the candidates
+        // are within r_couple, and one round of dependent loads is saved
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u) {
           if (ok[u]) {
             dx[u] = P.sx[j[u]];
             dy[u] = P.sy[j[u]];
             dz[u] = P.sz[j[u]];
+            rh[u] = P.rho[j[u]];
+            vx[u] = P.svx[j[u]];
+            vy[u] = P.svy[j[u]];
+            vz[u] = P.svz[j[u]];
           }
         }
 #pragma unroll
@@ -225,15 +232,6 @@ __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
             dz[u] -= ya[2];
             r2[u] = dist2_exact(dx[u], dy[u], dz[u]);
             in[u] = r2[u] < rc2;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kGatherBatch; ++u) {
-          if (in[u]) {
-            rh[u] = P.rho[j[u]];
-            vx[u] = P.svx[j[u]];
-            vy[u] = P.svy[j[u]];
-            vz[u] = P.svz[j[u]];
           }
         }
 #pragma unroll
