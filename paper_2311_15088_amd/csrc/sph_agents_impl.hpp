@@ -17,12 +17,13 @@ namespace sph {
 // cell-sorted arrays.  The wave concatenates the rows of a stencil (lane r
 // holds row r; an exclusive scan of the lengths goes to LDS) and lane l takes
 // elements l, l + 64, ... of the concatenation, kGatherBatch at a time with
-// all their position loads in flight together; the rest of an element is
-// loaded only when it is within range.  Each lane sums its elements in that
+// all their loads in flight together (the coupling gather loads a fluid
+// element's density and velocity with its position; the boid gather loads an
+// agent's velocity only when it is within range).  Each lane sums its elements in that
 // order and the wave reductions run in a fixed order, so the results are
 // deterministic.
 // ----------------------------------------------------------------------------
-constexpr int kGatherBatch = 2;
+constexpr int kGatherBatch = 3;
 
 template <int BD>
 __device__ __forceinline__ void agents_block(const PhysPlan& P, uint32_t blk) {
