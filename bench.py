@@ -51,6 +51,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, GB/s
 # it (78.6 TFLOP/s) is the attainable ceiling; the published figure is the peak.
 PEAK_FP32_TFLOPS = 157.3
 ATTAINABLE_FP32_TFLOPS = 78.6
+# dense bf16 MFMA peak of MI355X (without structured sparsity), TFLOP/s
+PEAK_BF16_TFLOPS = 2500.0
 
 # Algorithmic FP32 operations of the force + integration pass: per neighbour
 # pair (i, j in N_i) the pair term of the pressure and viscosity forces
@@ -433,11 +435,31 @@ def closure_leg(sph, scenes, torch, args):
     cl = sph.Closure(scenes.mlp_flat(scenes.mlp_init()), stream=stream)
     rep = cl.train(X, F, epochs=args.epochs, batch=4096, lr=1e-3, val_fraction=0.1, seed=7)
     log(f"[bench] closure: trained {rep}")
-    del X, F
+    # MFMA roofline of the network's forward pass (bf16 MFMA GEMMs with fused
+    # bias and GELU epilogues): 65,536 rows, as many as config 4 has agents
+    rows = min(65536, got)
+    xf = X[:rows].contiguous()
+    out = torch.empty((rows, 3), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        cl.predict(xf, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        cl.predict(xf, out)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    flop = 2.0 * (256 * 128 + 128 * 128 + 128 * 3) * rows
+    mlp = {"rows": rows, "gflop": flop / 1e9, "us": us, "achieved_tflops": flop / (us * 1e-6) / 1e12,
+           "peak_tflops": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "bound": "mfma"}
+    mlp["frac"] = mlp["achieved_tflops"] / PEAK_BF16_TFLOPS
+    log(f"[bench] closure: forward of {rows} rows in {us:.1f} us = {mlp['achieved_tflops']:.1f} TFLOP/s")
+    del X, F, xf, out
     # evaluation run: the workload itself, exact gather vs closure
     sc = scenes.config4()
     K = args.closure_steps
-    res = {"pairs": got, "collect_s": t_collect, "train": rep, "steps": K}
+    res = {"pairs": got, "collect_s": t_collect, "train": rep, "steps": K, "mlp_forward_roofline": mlp}
     # exact gather; the closure under its controller (2 % bound, check every
     # 50 steps); the closure with an unbounded threshold, which times the
     # surrogate path whatever its error
