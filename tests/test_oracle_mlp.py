@@ -129,3 +129,34 @@ def test_features_against_brute_force_binning():
             else:
                 np.testing.assert_array_equal(f[a, 4 * q + 1:4 * q + 4], 0.0)
     assert (f[:, 0::4] > 0).any()
+
+
+def test_bfloat16_forward_layers_within_their_rounding_error_bounds():
+    """Each layer of the bfloat16 forward computes the exact layer of its own
+    inputs up to one rounding to bfloat16 (unit roundoff 2^-8, plus 2^-23 for
+    the float32 step the rounding goes through) of every input and weight of
+    the products, and of every hidden activation after GELU.  The bounds
+    are checked element by element; at these sizes they are small next to a
+    bias term, so a dropped bias, a missing GELU or a transposed W2 fails."""
+    p, X, _ = _small_problem(seed=11, B=64)
+    X = 3.0 * X
+    for k in ("b1", "b2", "b3"):
+        p[k] = 10.0 * p[k]  # biases of order 1
+    Y, c = mlp.forward(p, X, mirror=True)
+    u = 2.0 ** -8 + 2.0 ** -23
+    a = np.abs
+    checks = [
+        (c["Z1"], X @ p["W1"] + p["b1"], (2 * u + u * u) * (a(X) @ a(p["W1"]))),
+        (c["H1"], mlp.gelu(c["Z1"]), u * a(mlp.gelu(c["Z1"]))),
+        (c["Z2"], c["H1"] @ p["W2"] + p["b2"], u * (a(c["H1"]) @ a(p["W2"]))),
+        (c["H2"], mlp.gelu(c["Z2"]), u * a(mlp.gelu(c["Z2"]))),
+        (Y, c["H2"] @ p["W3"] + p["b3"], u * (a(c["H2"]) @ a(p["W3"]))),
+    ]
+    for k, (got, exact, bound) in enumerate(checks):
+        err = a(got - exact)
+        assert np.all(err <= bound * (1 + 1e-9) + 1e-12), (k, float((err / (bound + 1e-30)).max()))
+    # the roundings act, and the layer bounds are tighter than the terms a slip would drop
+    assert a(Y - mlp.forward(p, X, mirror=False)[0]).max() > 0.0
+    for k, b in ((2, "b2"), (4, "b3")):
+        assert np.median(checks[k][2]) < 0.5 * np.median(a(p[b]))
+    assert a(c["H1"] @ p["W2"].T - c["H1"] @ p["W2"]).mean() > 10 * checks[2][2].mean()
