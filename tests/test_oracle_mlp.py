@@ -160,3 +160,34 @@ def test_bfloat16_forward_layers_within_their_rounding_error_bounds():
     for k, b in ((2, "b2"), (4, "b3")):
         assert np.median(checks[k][2]) < 0.5 * np.median(a(p[b]))
     assert a(c["H1"] @ p["W2"].T - c["H1"] @ p["W2"]).mean() > 10 * checks[2][2].mean()
+
+
+def test_bfloat16_gradients_within_their_rounding_error_bounds():
+    """The bfloat16 backward rounds the output gradient and each layer's
+    pre-activation gradient once to bfloat16 before the products (and uses
+    the forward's rounded weights and activations).  Against the exact
+    backward of the same forward activations, the gradients of W3 and W2 stay
+    within the first-order bound of those roundings, element by element."""
+    p, X, T = _small_problem(seed=13, B=64)
+    X = 3.0 * X
+    B = X.shape[0]
+    _, g = mlp.loss_and_grads(p, X, T, mirror=True)
+    Y, c = mlp.forward(p, X, mirror=True)
+    u = 2.0 ** -8 + 2.0 ** -23
+    a = np.abs
+    dY = 2.0 * (Y - T) / (3.0 * B)
+    # W3: one rounding of dY
+    bound3 = u * (a(c["H2"]).T @ a(dY))
+    err3 = a(g["W3"] - c["H2"].T @ dY)
+    assert np.all(err3 <= bound3 * (1 + 1e-9) + 1e-15)
+    # W2: roundings of dY and W3 in the pre-activation gradient, then of that gradient
+    gp = mlp.gelu_grad(c["Z2"])
+    dZ2 = (dY @ p["W3"].T) * gp
+    E = (2 * u + u * u) * (a(dY) @ a(p["W3"]).T) * a(gp)
+    bound2 = a(c["H1"]).T @ (E + u * (a(dZ2) + E))
+    err2 = a(g["W2"] - c["H1"].T @ dZ2)
+    assert np.all(err2 <= bound2 * (1 + 1e-9) + 1e-15)
+    assert err2.max() > 0.0 and err3.max() > 0.0
+    # tighter than the gradient itself: a wrong operand would not fit
+    assert np.median(bound2) < 0.2 * np.median(a(c["H1"].T @ dZ2))
+    assert np.median(bound3) < 0.2 * np.median(a(c["H2"].T @ dY))
