@@ -178,7 +178,9 @@ sph_status sph_capture(sph_ctx* ctx, int32_t n_steps);
    launch per step (variant = LDS capacities).  tile_x = grid cells along x
    that one workgroup of the fluid passes takes at a time (1 ..
    sph_variant_tile_max: 32, or 64 for the variants with tables that wide).
-   Every form gives bit-identical results; only the speed differs. */
+   Every form gives bit-identical results; only the speed differs.  A context
+   starts with fused = 0, variant 1 (256-thread blocks in both fluid passes),
+   tile_x = 32. */
 typedef struct sph_tuning {
   int32_t fused, variant, tile_x;
   float ms_per_step; /* measured by sph_autotune (0 when set by hand) */

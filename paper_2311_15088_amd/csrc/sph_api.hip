@@ -255,7 +255,7 @@ sph_status sph_ctx_build(const std::vector<sph_params>& params, const std::vecto
   ctx->nsets = nsets;
   ctx->nchunks = chunk_prefix[nsets];
   // tile width and kernel variant (SPH_TILE_X, SPH_FLUID_VARIANT override the defaults)
-  int variant = 0;
+  int variant = fluid_default_variant();
   if (const char* e = getenv("SPH_FLUID_VARIANT")) variant = std::max(0, std::min(fluid_variants() - 1, atoi(e)));
   int tx = fluid_tile_max(0, variant);  // the variant's widest tile
   if (const char* e = getenv("SPH_TILE_X")) tx = std::max(1, std::min(fluid_tile_max(0, variant), atoi(e)));

@@ -106,6 +106,8 @@ uint32_t scan_chunks(uint32_t ncells);
 constexpr int kStepPhases = kSortPhases + 3;
 uint32_t fluid_tiles(const DGrid& g, int tx, int ty = 1);
 int fluid_variants();
+// Kernel variant of the per-phase form a context starts with.
+int fluid_default_variant();
 // particles per work item of the fluid passes: the block size of the form
 int fluid_item_max(int fused, int variant);
 // Widest tile (cells along x) a kernel variant's LDS tables hold.
