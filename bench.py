@@ -74,9 +74,9 @@ B_ALG_PASS = {"density": 18, "force_integrate": 52}
 # plain device copy of known size), averaged over the timed steps of the run
 # named; valid only for the kernel sources it was measured on.
 TRAFFIC = {
-    "density": {"sources_sha256_16": "ac1cdcff01c1cd7a", "bytes_per_launch": 103.3e6,
+    "density": {"sources_sha256_16": "af7bd13abb1d2cc7", "bytes_per_launch": 106.6e6,
                 "run": "bench.py --plain-steps 1025, dispatches 26-1025 (profiles/fluid_counters_dam_break_1M.md)"},
-    "force_integrate": {"sources_sha256_16": "ac1cdcff01c1cd7a", "bytes_per_launch": 193.9e6,
+    "force_integrate": {"sources_sha256_16": "af7bd13abb1d2cc7", "bytes_per_launch": 196.2e6,
                         "run": "bench.py --plain-steps 1025, dispatches 26-1025 (profiles/fluid_counters_dam_break_1M.md)"},
 }
 FLUID_SOURCES = ("paper_2311_15088_amd/csrc/sph_fluid_impl.hpp", "paper_2311_15088_amd/csrc/sph_physics.hip",
