@@ -211,3 +211,18 @@ def test_abort_flag_does_not_touch_per_phase_steps():
     same(state(ref), state(sim))
     ref.close()
     sim.close()
+
+
+def test_default_form_is_the_documented_one_and_equals_variant_zero():
+    """A context starts in the per-phase form with variant 1 (256-thread
+    blocks in both fluid passes) and 32-cell tiles, and steps bit-identically
+    to the 512-thread density form (variant 0)."""
+    sc = scenes.config0c()
+    sim = sph.create(sc)
+    t = sim.tuning()
+    assert (t["fused"], t["variant"], t["tile_x"]) == (0, 1, 32)
+    assert sph.variant_name(0, t["variant"]) == "bd256_win512_512"
+    sim.step(3)
+    got = state(sim)
+    sim.close()
+    same(got, run(sc, 3, fused=0, variant=0, tile_x=32))
